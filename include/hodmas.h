@@ -1,0 +1,200 @@
+/*
+ * hodmas.h -- C ABI of the MI355X (gfx950) higher-order delay-multiply-and-sum
+ * (HO-DMAS) photoacoustic beamformer.
+ *
+ * The library forms an image from linear-array photoacoustic RF data.  For each
+ * pixel p and each element i it takes the channel sample at the pixel's one-way
+ * time of flight (delay of Eq. 1, Sec. II-A), linearly interpolated, forms the
+ * signed k-th root y_i = sign(s_i)|s_i|^(1/k) (Eq. 2, Eqs. 4-6), and outputs
+ *
+ *     S_k(p) = sum over all k-subsets I of the channels of prod_{i in I} y_i,
+ *
+ * which is DAS for k = 1 (Eq. 1), DMAS for k = 2 (Eq. 2) and DMAS-3/4/5 for
+ * k = 3..5 (Eqs. 4-6); k = 6 is the same definition one order higher (Sec. VI).
+ * The sum is evaluated in O(N) per pixel from the power sums
+ * p_j = sum_i y_i^j, as the paper's simplified forms do (Eqs. 3, 7, 8, 9).
+ *
+ * Conventions shared by every call:
+ *   - Delay of element i for pixel (x, z), in samples:
+ *         t = fs * (sqrt((x - x_i)^2 + z^2) / c - t0).
+ *     Elements sit at z = 0; pixels at z > 0 face the array.
+ *   - Sample at fractional index t: (1-f) s[j] + f s[j+1], j = floor(t),
+ *     f = t - j; t outside [0, S-1] contributes 0 (the channel drops out of
+ *     every product for that pixel); t == S-1 gives s[S-1].
+ *   - RF is channel-major: element i's record starts at rf + i*channel_stride
+ *     (in elements of the RF dtype), samples contiguous.
+ *   - The image is row-major float32 [nz][nx]: pixel (ix, iz) at
+ *     (x0 + ix*dx, z0 + iz*dz) is stored at image[iz*nx + ix].
+ *   - No order normalisation, apodisation or envelope is applied: the value is
+ *     the raw symmetric sum, with the same units as the RF (degree-1 in s).
+ *
+ * Errors: every entry point returns a hodmas_status.  Argument errors are
+ * detected on the host before anything is launched and leave all outputs
+ * untouched.  Launch failures are HODMAS_EDEVICE.  Faults inside an already
+ * launched kernel surface as HIP errors on the caller's stream, as for any
+ * other HIP work.  No C++ exception or abort crosses this interface.
+ *
+ * Threading: a plan is immutable after creation.  Concurrent hodmas_beamform
+ * calls with the same plan on different streams are allowed.
+ */
+#ifndef HODMAS_H
+#define HODMAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HODMAS_OK = 0,
+    HODMAS_EINVAL = 1,          /* bad argument: null pointer, size, geometry */
+    HODMAS_ENOMEM = 2,          /* host or device allocation failed */
+    HODMAS_EDEVICE = 3,         /* HIP runtime error (no device, launch failed) */
+    HODMAS_EUNSUPPORTED = 4,    /* valid request outside this build (order > max) */
+    HODMAS_EBUSY = 5            /* resource held by another in-flight request */
+} hodmas_status;
+
+typedef enum {
+    HODMAS_F32 = 0,             /* IEEE float32 samples */
+    HODMAS_F16 = 1,             /* IEEE float16 samples */
+    HODMAS_I16 = 2              /* int16 ADC codes; sample = code * dequant_scale */
+} hodmas_dtype;
+
+/* Limits of this build. */
+#define HODMAS_MAX_ORDER 6
+#define HODMAS_MAX_ELEMENTS 4096
+#define HODMAS_MAX_SAMPLES (1 << 24)     /* sample indices stay exact in float32 */
+#define HODMAS_MAX_GRID_SIDE 16384
+
+/* Plan flags. */
+#define HODMAS_FLAG_ACC_PLAIN   0x1u  /* plain float32 power sums (default: compensated) */
+#define HODMAS_FLAG_HOST_ONLY   0x2u  /* build host tables only; no device use (inspection) */
+#define HODMAS_FLAG_FORCE_CHECK 0x4u  /* always run the record-boundary test per sample */
+
+/* Linear array.  element_x_m == NULL means a centred uniform array,
+ * x_i = (i - (n_elements-1)/2) * pitch_m.  The pointer is read during
+ * hodmas_plan only (host memory). */
+typedef struct {
+    int32_t n_elements;
+    double pitch_m;
+    double sound_speed_m_s;
+    double fs_hz;
+    double t0_s;                 /* time of the first sample after the laser shot */
+    const double* element_x_m;   /* optional, host, n_elements entries */
+} hodmas_geometry;
+
+/* Image grid: pixel (ix, iz) centre at (x0_m + ix*dx_m, z0_m + iz*dz_m). */
+typedef struct {
+    int32_t nx, nz;
+    double x0_m, dx_m;
+    double z0_m, dz_m;
+} hodmas_grid;
+
+/* RF storage.  frame_max is any positive bound on |sample| after
+ * dequantisation (0 means 1); samples are divided by it inside the kernel so the
+ * power sums stay in range, and the result is multiplied back, so the value of
+ * frame_max changes only rounding. */
+typedef struct {
+    int32_t dtype;               /* hodmas_dtype */
+    int32_t n_samples;           /* S, samples per channel */
+    int64_t channel_stride;      /* elements between channel records, >= S */
+    float dequant_scale;         /* I16 only: value of one code, > 0 */
+    float frame_max;             /* >= 0; 0 means 1 */
+} hodmas_rf_desc;
+
+/* Tiling of a plan.  Zero fields are chosen by the library. */
+typedef struct {
+    int32_t tile_x;              /* pixels per tile along x */
+    int32_t tile_z;              /* pixels per tile along z */
+    int32_t split;               /* waves sharing one pixel's channels: 1, 2 or 4 */
+    int32_t chunk;               /* channels staged in LDS at a time */
+} hodmas_tiling;
+
+typedef struct hodmas_plan_s* hodmas_plan_t;
+
+/* Create a plan for one array geometry, image grid and RF layout.
+ * Computes, in float64 on the host, the per-(tile, channel) delay anchors and
+ * LDS sample windows the kernel uses (the paper precomputes delays before the
+ * kernel call, Sec. V), and copies them to the current HIP device once.
+ * max_order in [1, HODMAS_MAX_ORDER].  tiling may be NULL (library default).
+ * Pixels must lie in front of the array (z0_m > 0, dz_m > 0) and dx_m > 0.
+ * On success *out owns its device tables until hodmas_destroy.
+ * Errors: EINVAL (null pointer, non-positive or non-finite sizes/speeds, stride
+ * < S, limits above exceeded, bad tiling), ENOMEM, EDEVICE. */
+hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* grid,
+                          const hodmas_rf_desc* rf, int32_t max_order, uint32_t flags,
+                          const hodmas_tiling* tiling, hodmas_plan_t* out);
+
+/* Beamform one frame at order k (1 = DAS, 2 = DMAS, 3..6 = DMAS-k; Eqs. 1-9).
+ * rf_dev: device pointer, channel-major records of the plan's dtype and stride.
+ * image_dev: device float32 [nz][nx], fully overwritten.  Both are owned by the
+ * caller and must stay valid until the work on `stream` completes.
+ * stream: a hipStream_t (NULL = default stream).  Asynchronous; one kernel
+ * launch; no allocation.  Errors: EINVAL (null plan/pointers, host-only plan),
+ * EUNSUPPORTED (order outside [1, min(6, max_order)]), EDEVICE (launch). */
+hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t order,
+                              float* image_dev, void* stream);
+
+/* Release a plan and its device tables.  NULL is accepted.  The caller must
+ * not destroy a plan while work launched with it may still be running. */
+hodmas_status hodmas_destroy(hodmas_plan_t plan);
+
+/* Static description of a status code (never NULL). */
+const char* hodmas_status_string(hodmas_status status);
+
+/* Plan summary, for callers that size work or report throughput. */
+typedef struct {
+    int32_t n_elements, n_samples, nx, nz;
+    int32_t max_order, dtype;
+    hodmas_tiling tiling;
+    int32_t n_tiles;             /* tiles covering the grid */
+    int32_t max_window;          /* longest LDS sample window of any tile */
+    int64_t active_pairs;        /* (tile, channel) pairs that touch the record */
+    int64_t lds_bytes;           /* dynamic LDS per workgroup */
+    int64_t table_bytes;         /* device bytes held by the plan */
+    uint32_t flags;
+} hodmas_plan_info;
+
+hodmas_status hodmas_plan_get_info(hodmas_plan_t plan, hodmas_plan_info* info);
+
+/* Inspection of the host copy of the plan tables (layouts below), for tests
+ * of the plan's float64 geometry.  Pointers stay valid until hodmas_destroy. */
+typedef struct {
+    int32_t ix0, iz0;            /* first pixel of the tile */
+    int32_t nx, nz;              /* pixels of the tile inside the grid */
+    int32_t n_active;            /* channels with any delay inside the record */
+    int32_t window;              /* LDS samples per channel for this tile */
+    int32_t check;               /* 1: some delay may fall outside [0, S-1] */
+    int32_t first_entry;         /* index of the tile's first channel entry */
+    double xa, za;               /* anchor pixel, in samples of one-way flight */
+} hodmas_tile_desc;
+
+typedef struct {
+    float a;                     /* anchor x minus element x (samples) */
+    float d0sq;                  /* anchor-to-element distance squared */
+    float d0;                    /* anchor-to-element distance */
+    float frac0;                 /* fractional part of the anchor delay */
+    float lo, hi;                /* valid delays relative to floor(anchor delay) */
+    int32_t off;                 /* LDS index of floor(anchor delay) */
+    int32_t channel;             /* element index */
+} hodmas_chan_entry;
+
+typedef struct {
+    int32_t channel;             /* element index */
+    int32_t first_sample;        /* record index of LDS window position 0 */
+} hodmas_stage_entry;
+
+hodmas_status hodmas_plan_tables(hodmas_plan_t plan, const hodmas_tile_desc** tiles,
+                                 const hodmas_chan_entry** entries,
+                                 const hodmas_stage_entry** stage, int32_t* n_tiles,
+                                 int64_t* n_entries);
+
+/* Version string of the library. */
+const char* hodmas_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HODMAS_H */

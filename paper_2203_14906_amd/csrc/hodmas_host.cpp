@@ -1,0 +1,457 @@
+// Host side of the HO-DMAS library: argument validation, the float64 plan
+// (per-tile delay anchors and LDS sample windows) and the C ABI entry points.
+//
+// The paper computes every (pixel, element) delay on the CPU before the kernel
+// call and keeps it in GPU memory (Sec. V).  Here the plan keeps only one
+// float64-derived anchor per (tile, element); the kernel rebuilds each pixel's
+// delay from it in registers.  Per pixel this is t = T0 + frac0 + (d - d0) with
+// d - d0 = (d^2 - d0^2) / (d + d0), which keeps the delay's rounding error
+// proportional to the small in-tile offset instead of to the full flight time.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hodmas_internal.h"
+
+using hodmas::FrameArgs;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x484f444du;  // "HODM"
+constexpr double kMaxDistanceSamples = 4194304.0;  // 2^22: delays stay exact-integer in float32
+
+}  // namespace
+
+struct hodmas_plan_s {
+    uint32_t magic = kMagic;
+    hodmas_geometry geom{};
+    hodmas_grid grid{};
+    hodmas_rf_desc rf{};
+    int32_t max_order = 0;
+    uint32_t flags = 0;
+    hodmas_tiling tiling{};
+    std::vector<double> elem_x;           // metres
+    double x0s = 0, dxs = 0, z0s = 0, dzs = 0, t0s = 0;
+    std::vector<hodmas_tile_desc> tiles;
+    std::vector<hodmas_chan_entry> entries;
+    std::vector<hodmas_stage_entry> stage;
+    int32_t max_window = 0;
+    int64_t lds_bytes = 0;
+    float in_scale = 1.f, out_scale = 1.f;
+    int device = -1;
+    hodmas_tile_desc* d_tiles = nullptr;
+    hodmas_chan_entry* d_entries = nullptr;
+    hodmas_stage_entry* d_stage = nullptr;
+    int64_t table_bytes = 0;
+};
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+hodmas_status validate(const hodmas_geometry* g, const hodmas_grid* gr, const hodmas_rf_desc* rf,
+                       int32_t max_order, const hodmas_tiling* t)
+{
+    if (!g || !gr || !rf)
+        return HODMAS_EINVAL;
+    if (g->n_elements < 1 || g->n_elements > HODMAS_MAX_ELEMENTS)
+        return HODMAS_EINVAL;
+    if (!finite_pos(g->sound_speed_m_s) || !finite_pos(g->fs_hz) || !std::isfinite(g->t0_s))
+        return HODMAS_EINVAL;
+    if (g->element_x_m) {
+        for (int i = 0; i < g->n_elements; ++i)
+            if (!std::isfinite(g->element_x_m[i]))
+                return HODMAS_EINVAL;
+    } else if (!finite_pos(g->pitch_m)) {
+        return HODMAS_EINVAL;
+    }
+    if (gr->nx < 1 || gr->nz < 1 || gr->nx > HODMAS_MAX_GRID_SIDE || gr->nz > HODMAS_MAX_GRID_SIDE)
+        return HODMAS_EINVAL;
+    if (!std::isfinite(gr->x0_m) || !finite_pos(gr->dx_m) || !finite_pos(gr->z0_m) ||
+        !finite_pos(gr->dz_m))
+        return HODMAS_EINVAL;
+    if (rf->dtype != HODMAS_F32 && rf->dtype != HODMAS_F16 && rf->dtype != HODMAS_I16)
+        return HODMAS_EINVAL;
+    if (rf->n_samples < 1 || rf->n_samples > HODMAS_MAX_SAMPLES || rf->channel_stride < rf->n_samples)
+        return HODMAS_EINVAL;
+    if (rf->channel_stride > (int64_t(1) << 40))
+        return HODMAS_EINVAL;
+    if (rf->dtype == HODMAS_I16 && !finite_pos(rf->dequant_scale))
+        return HODMAS_EINVAL;
+    if (!std::isfinite(rf->frame_max) || rf->frame_max < 0.f)
+        return HODMAS_EINVAL;
+    if (max_order < 1 || max_order > HODMAS_MAX_ORDER)
+        return HODMAS_EINVAL;
+    if (t) {
+        bool any = t->tile_x || t->tile_z || t->split || t->chunk;
+        if (any) {
+            if (t->tile_x < 1 || t->tile_z < 1 || t->chunk < 0)
+                return HODMAS_EINVAL;
+            if (t->split != 1 && t->split != 2 && t->split != 4)
+                return HODMAS_EINVAL;
+            if (int64_t(t->tile_x) * t->tile_z * t->split != hodmas::kBlock)
+                return HODMAS_EINVAL;
+        }
+    }
+    return HODMAS_OK;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Library default: 16x16 pixel tiles; split the channels of a pixel over 2 or 4
+// waves when the grid has too few tiles to give every CU a few workgroups.
+hodmas_tiling default_tiling(const hodmas_grid& gr)
+{
+    const int64_t want = 2 * 256;  // two workgroups per CU
+    hodmas_tiling t{16, 16, 1, 64};
+    if (ceil_div(gr.nx, 16) * ceil_div(gr.nz, 16) >= want)
+        return t;
+    t = {16, 8, 2, 64};
+    if (ceil_div(gr.nx, 16) * ceil_div(gr.nz, 8) >= want)
+        return t;
+    return {8, 8, 4, 64};
+}
+
+void free_device(hodmas_plan_s* p)
+{
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_entries) (void)hipFree(p->d_entries);
+    if (p->d_stage) (void)hipFree(p->d_stage);
+    p->d_tiles = nullptr;
+    p->d_entries = nullptr;
+    p->d_stage = nullptr;
+}
+
+// Build the per-tile tables in float64.  For every tile and element:
+//   anchor delay ta = |anchor - element| - t0 (samples), T0 = floor(ta);
+//   the delay range [tmin, tmax] over the tile's pixel rectangle (closed form:
+//   nearest and farthest points of the rectangle), which bounds the LDS window;
+//   elements whose whole range misses [0, S-1] are left out (they contribute 0).
+hodmas_status build_tables(hodmas_plan_s* p)
+{
+    const hodmas_grid& gr = p->grid;
+    const int n = p->geom.n_elements;
+    const int S = p->rf.n_samples;
+    const int tx = p->tiling.tile_x, tz = p->tiling.tile_z;
+    const int ntx = (int)ceil_div(gr.nx, tx), ntz = (int)ceil_div(gr.nz, tz);
+    const double lam = p->geom.sound_speed_m_s / p->geom.fs_hz;  // metres per sample
+    p->x0s = gr.x0_m / lam;
+    p->dxs = gr.dx_m / lam;
+    p->z0s = gr.z0_m / lam;
+    p->dzs = gr.dz_m / lam;
+    p->t0s = p->geom.t0_s * p->geom.fs_hz;
+    std::vector<double> xe(n);
+    for (int i = 0; i < n; ++i)
+        xe[i] = p->elem_x[i] / lam;
+
+    // every delay must stay far inside float32's exact-integer range
+    double xmin = *std::min_element(xe.begin(), xe.end()), xmax = *std::max_element(xe.begin(), xe.end());
+    double gx_lo = p->x0s, gx_hi = p->x0s + (gr.nx - 1) * p->dxs;
+    double gz_hi = p->z0s + (gr.nz - 1) * p->dzs;
+    double far = std::sqrt(std::pow(std::max(std::fabs(gx_hi - xmin), std::fabs(gx_lo - xmax)), 2) +
+                           gz_hi * gz_hi) + std::fabs(p->t0s);
+    if (!(far < kMaxDistanceSamples))
+        return HODMAS_EINVAL;
+
+    try {
+        p->tiles.assign((size_t)ntx * ntz, hodmas_tile_desc{});
+        p->entries.clear();
+        p->stage.clear();
+        p->entries.reserve((size_t)ntx * ntz * n);
+        p->stage.reserve((size_t)ntx * ntz * n);
+    } catch (const std::bad_alloc&) {
+        return HODMAS_ENOMEM;
+    }
+    const int chunk = p->tiling.chunk;
+    int32_t max_window = 2;
+    std::vector<int32_t> T0(n), wlo(n), whi(n);
+    std::vector<float> fr(n), aa(n), d0sq(n), d0(n);
+    std::vector<char> act(n), chk(n);
+    for (int bz = 0; bz < ntz; ++bz) {
+        for (int bx = 0; bx < ntx; ++bx) {
+            hodmas_tile_desc& td = p->tiles[(size_t)bz * ntx + bx];
+            td.ix0 = bx * tx;
+            td.iz0 = bz * tz;
+            td.nx = std::min(tx, gr.nx - td.ix0);
+            td.nz = std::min(tz, gr.nz - td.iz0);
+            const int ia = td.ix0 + (td.nx - 1) / 2, ja = td.iz0 + (td.nz - 1) / 2;
+            td.xa = p->x0s + ia * p->dxs;
+            td.za = p->z0s + ja * p->dzs;
+            const double xlo = p->x0s + td.ix0 * p->dxs, xhi = p->x0s + (td.ix0 + td.nx - 1) * p->dxs;
+            const double zlo = p->z0s + td.iz0 * p->dzs, zhi = p->z0s + (td.iz0 + td.nz - 1) * p->dzs;
+            int32_t window = 2;
+            int32_t n_active = 0;
+            bool check = (p->flags & HODMAS_FLAG_FORCE_CHECK) != 0;
+            for (int i = 0; i < n; ++i) {
+                const double a = td.xa - xe[i];
+                const double sq = a * a + td.za * td.za;
+                const double d = std::sqrt(sq);
+                const double ta = d - p->t0s;
+                const double fl = std::floor(ta);
+                const double dxn = xe[i] < xlo ? xlo - xe[i] : (xe[i] > xhi ? xe[i] - xhi : 0.0);
+                const double dxf = std::max(std::fabs(xlo - xe[i]), std::fabs(xhi - xe[i]));
+                const double tmin = std::sqrt(dxn * dxn + zlo * zlo) - p->t0s;
+                const double tmax = std::sqrt(dxf * dxf + zhi * zhi) - p->t0s;
+                act[i] = !(tmax < 0.0 || tmin > double(S - 1));
+                if (!act[i])
+                    continue;
+                ++n_active;
+                chk[i] = (tmin < 0.5 || tmax > double(S - 1) - 0.5);
+                check = check || chk[i];
+                T0[i] = (int32_t)fl;
+                fr[i] = (float)(ta - fl);
+                aa[i] = (float)a;
+                d0sq[i] = (float)sq;
+                d0[i] = (float)d;
+                wlo[i] = (int32_t)std::floor(tmin) - 1;
+                whi[i] = (int32_t)std::floor(tmax) + 2;
+                window = std::max(window, whi[i] - wlo[i] + 1);
+            }
+            td.n_active = n_active;
+            td.window = window;
+            td.check = check ? 1 : 0;
+            td.first_entry = (int32_t)p->entries.size();
+            max_window = std::max(max_window, window);
+            int slot = 0;
+            for (int i = 0; i < n; ++i) {
+                if (!act[i])
+                    continue;
+                hodmas_chan_entry e;
+                e.a = aa[i];
+                e.d0sq = d0sq[i];
+                e.d0 = d0[i];
+                e.frac0 = fr[i];
+                e.lo = (float)(-(double)T0[i]);
+                e.hi = (float)((double)(S - 1) - (double)T0[i]);
+                e.off = T0[i] - wlo[i] + (slot % chunk) * window;
+                e.channel = i;
+                p->entries.push_back(e);
+                p->stage.push_back(hodmas_stage_entry{i, wlo[i]});
+                ++slot;
+            }
+        }
+    }
+    p->max_window = max_window;
+    return HODMAS_OK;
+}
+
+hodmas_status upload(hodmas_plan_s* p)
+{
+    if (hipGetDevice(&p->device) != hipSuccess)
+        return HODMAS_EDEVICE;
+    size_t tb = p->tiles.size() * sizeof(hodmas_tile_desc);
+    size_t eb = std::max<size_t>(p->entries.size(), 1) * sizeof(hodmas_chan_entry);
+    size_t sb = std::max<size_t>(p->stage.size(), 1) * sizeof(hodmas_stage_entry);
+    if (hipMalloc((void**)&p->d_tiles, tb) != hipSuccess ||
+        hipMalloc((void**)&p->d_entries, eb) != hipSuccess ||
+        hipMalloc((void**)&p->d_stage, sb) != hipSuccess) {
+        free_device(p);
+        (void)hipGetLastError();
+        return HODMAS_ENOMEM;
+    }
+    if (hipMemcpy(p->d_tiles, p->tiles.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
+        (!p->entries.empty() &&
+         hipMemcpy(p->d_entries, p->entries.data(), p->entries.size() * sizeof(hodmas_chan_entry),
+                   hipMemcpyHostToDevice) != hipSuccess) ||
+        (!p->stage.empty() &&
+         hipMemcpy(p->d_stage, p->stage.data(), p->stage.size() * sizeof(hodmas_stage_entry),
+                   hipMemcpyHostToDevice) != hipSuccess)) {
+        free_device(p);
+        (void)hipGetLastError();
+        return HODMAS_EDEVICE;
+    }
+    p->table_bytes = (int64_t)(tb + eb + sb);
+    return HODMAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* grid,
+                          const hodmas_rf_desc* rf, int32_t max_order, uint32_t flags,
+                          const hodmas_tiling* tiling, hodmas_plan_t* out)
+{
+    if (!out)
+        return HODMAS_EINVAL;
+    *out = nullptr;
+    hodmas_status st = validate(geometry, grid, rf, max_order, tiling);
+    if (st != HODMAS_OK)
+        return st;
+    hodmas_plan_s* p = new (std::nothrow) hodmas_plan_s;
+    if (!p)
+        return HODMAS_ENOMEM;
+    p->geom = *geometry;
+    p->geom.element_x_m = nullptr;
+    p->grid = *grid;
+    p->rf = *rf;
+    p->max_order = max_order;
+    p->flags = flags;
+    try {
+        p->elem_x.resize(geometry->n_elements);
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return HODMAS_ENOMEM;
+    }
+    for (int i = 0; i < geometry->n_elements; ++i)
+        p->elem_x[i] = geometry->element_x_m
+                           ? geometry->element_x_m[i]
+                           : (i - (geometry->n_elements - 1) / 2.0) * geometry->pitch_m;
+    bool given = tiling && (tiling->tile_x || tiling->tile_z || tiling->split || tiling->chunk);
+    p->tiling = given ? *tiling : default_tiling(*grid);
+    if (p->tiling.chunk == 0)
+        p->tiling.chunk = 64;
+    st = build_tables(p);
+    if (st != HODMAS_OK) {
+        delete p;
+        return st;
+    }
+    // LDS: `chunk` windows of `max_window` floats; shrink the chunk until it fits.
+    const int64_t reduce_bytes = int64_t(hodmas::kBlock / p->tiling.split) * (p->tiling.split - 1) *
+                                 HODMAS_MAX_ORDER * 2 * 4;
+    const int64_t cap = 64 * 1024;
+    if (int64_t(p->max_window) * 4 > hodmas::kMaxLdsBytes) {
+        delete p;
+        return HODMAS_EUNSUPPORTED;
+    }
+    if (int64_t(p->tiling.chunk) * p->max_window * 4 > cap) {
+        int c = (int)std::max<int64_t>(1, cap / (int64_t(p->max_window) * 4));
+        p->tiling.chunk = c;
+        st = build_tables(p);  // entry offsets depend on the chunk
+        if (st != HODMAS_OK) {
+            delete p;
+            return st;
+        }
+    }
+    p->lds_bytes = std::max<int64_t>(int64_t(p->tiling.chunk) * p->max_window * 4, reduce_bytes);
+    const double fm = rf->frame_max > 0.f ? (double)rf->frame_max : 1.0;
+    const double dq = rf->dtype == HODMAS_I16 ? (double)rf->dequant_scale : 1.0;
+    p->in_scale = (float)(dq / fm);
+    p->out_scale = (float)fm;
+    if (!(flags & HODMAS_FLAG_HOST_ONLY)) {
+        st = upload(p);
+        if (st != HODMAS_OK) {
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t order,
+                              float* image_dev, void* stream)
+{
+    if (!plan || plan->magic != kMagic || !rf_dev || !image_dev)
+        return HODMAS_EINVAL;
+    if (plan->flags & HODMAS_FLAG_HOST_ONLY)
+        return HODMAS_EINVAL;
+    if (order < 1 || order > plan->max_order || order > HODMAS_MAX_ORDER)
+        return HODMAS_EUNSUPPORTED;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return HODMAS_EDEVICE;
+    if (cur != plan->device && hipSetDevice(plan->device) != hipSuccess)
+        return HODMAS_EDEVICE;
+    FrameArgs a;
+    a.tiles = plan->d_tiles;
+    a.entries = plan->d_entries;
+    a.stage = plan->d_stage;
+    a.rf = rf_dev;
+    a.image = image_dev;
+    a.stride = plan->rf.channel_stride;
+    a.n_samples = plan->rf.n_samples;
+    a.nx = plan->grid.nx;
+    a.nz = plan->grid.nz;
+    a.tile_x = plan->tiling.tile_x;
+    a.split = plan->tiling.split;
+    a.chunk = plan->tiling.chunk;
+    a.n_tiles = (int32_t)plan->tiles.size();
+    a.x0s = plan->x0s;
+    a.dxs = plan->dxs;
+    a.z0s = plan->z0s;
+    a.dzs = plan->dzs;
+    a.in_scale = plan->in_scale;
+    a.out_scale = plan->out_scale;
+    const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
+    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, plan->lds_bytes, stream);
+    if (cur != plan->device)
+        (void)hipSetDevice(cur);
+    return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
+}
+
+hodmas_status hodmas_destroy(hodmas_plan_t plan)
+{
+    if (!plan)
+        return HODMAS_OK;
+    if (plan->magic != kMagic)
+        return HODMAS_EINVAL;
+    int cur = -1;
+    bool switched = false;
+    if (plan->d_tiles && hipGetDevice(&cur) == hipSuccess && cur != plan->device)
+        switched = hipSetDevice(plan->device) == hipSuccess;
+    free_device(plan);
+    if (switched)
+        (void)hipSetDevice(cur);
+    plan->magic = 0;
+    delete plan;
+    return HODMAS_OK;
+}
+
+const char* hodmas_status_string(hodmas_status s)
+{
+    switch (s) {
+    case HODMAS_OK: return "ok";
+    case HODMAS_EINVAL: return "invalid argument";
+    case HODMAS_ENOMEM: return "out of memory";
+    case HODMAS_EDEVICE: return "HIP device error";
+    case HODMAS_EUNSUPPORTED: return "unsupported request";
+    case HODMAS_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+hodmas_status hodmas_plan_get_info(hodmas_plan_t plan, hodmas_plan_info* info)
+{
+    if (!plan || plan->magic != kMagic || !info)
+        return HODMAS_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n_elements = plan->geom.n_elements;
+    info->n_samples = plan->rf.n_samples;
+    info->nx = plan->grid.nx;
+    info->nz = plan->grid.nz;
+    info->max_order = plan->max_order;
+    info->dtype = plan->rf.dtype;
+    info->tiling = plan->tiling;
+    info->n_tiles = (int32_t)plan->tiles.size();
+    info->max_window = plan->max_window;
+    info->active_pairs = (int64_t)plan->entries.size();
+    info->lds_bytes = plan->lds_bytes;
+    info->table_bytes = plan->table_bytes;
+    info->flags = plan->flags;
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_plan_tables(hodmas_plan_t plan, const hodmas_tile_desc** tiles,
+                                 const hodmas_chan_entry** entries,
+                                 const hodmas_stage_entry** stage, int32_t* n_tiles,
+                                 int64_t* n_entries)
+{
+    if (!plan || plan->magic != kMagic || !tiles || !entries || !stage || !n_tiles || !n_entries)
+        return HODMAS_EINVAL;
+    *tiles = plan->tiles.data();
+    *entries = plan->entries.data();
+    *stage = plan->stage.data();
+    *n_tiles = (int32_t)plan->tiles.size();
+    *n_entries = (int64_t)plan->entries.size();
+    return HODMAS_OK;
+}
+
+const char* hodmas_version(void) { return "hodmas 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// Fused HO-DMAS beamforming kernel for gfx950 (MI355X).
+//
+// One workgroup (4 wave64) forms one pixel tile.  Per pixel and element it
+//   1. rebuilds the one-way delay from the tile's float64 anchor (registers),
+//   2. gathers the two neighbouring samples from an LDS window that the
+//      workgroup staged with coalesced channel-major loads, and interpolates,
+//   3. takes the signed k-th root y = sign(s)|s|^(1/k)       (Eq. 2, Eqs. 4-6),
+//   4. accumulates the power sums p_j = sum y^j, j = 1..k, with compensated
+//      float32 summation,
+// and per pixel recovers the order-k symmetric sum e_k from p_1..p_k with
+// Newton's identities (the general form of Eqs. 3, 7, 8 and 9):
+//   e_0 = 1,  m e_m = sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
+// The recovery runs in float32 for k <= 4 and in float64 for k >= 5, where the
+// alternating terms cancel more.  y^k is taken as the sample itself (odd k) or
+// its magnitude (even k), exactly as the paper's forms use sum s and sum |s|.
+//
+// Per-element constants are wave-uniform (every lane of a wave works on the same
+// element at the same time), so they live in SGPRs via scalar loads; the
+// per-pixel state lives in VGPRs.  No MFMA: this is gather + VALU work.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "hodmas_internal.h"
+
+namespace hodmas {
+namespace {
+
+// Read-only tables; wave-uniform indices let the compiler use scalar loads.
+using ConstTile = const hodmas_tile_desc* __restrict__;
+using ConstEntry = const hodmas_chan_entry* __restrict__;
+using ConstStage = const hodmas_stage_entry* __restrict__;
+
+template <int DT> struct Storage;
+template <> struct Storage<HODMAS_F32> { using T = float; };
+template <> struct Storage<HODMAS_F16> { using T = _Float16; };
+template <> struct Storage<HODMAS_I16> { using T = short; };
+
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ float widen(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float widen(short v) { return (float)v; }
+
+// Kahan step: s + x with the running compensation c (true sum ~ s - c).
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x)
+{
+    float y = x - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Delayed, interpolated sample of one element for this lane's pixel.
+template <bool CHECK>
+__device__ __forceinline__ float gather(const hodmas_chan_entry& e, float u2, float q,
+                                        const float* __restrict__ lds)
+{
+    // d^2 - d0^2 for this pixel, then d - d0 = (d^2 - d0^2) / (d + d0)
+    float num = __builtin_fmaf(u2, e.a, q);
+    float d = __builtin_amdgcn_sqrtf(__builtin_fabsf(e.d0sq + num));
+    float r = __builtin_amdgcn_rcpf(d + e.d0);
+    float t = __builtin_fmaf(num, r, e.frac0);      // delay minus floor(anchor delay)
+    float fl = __builtin_floorf(t);
+    float f = t - fl;
+    int idx = (int)fl + e.off;
+    float s0 = lds[idx];
+    float s1 = lds[idx + 1];
+    float v = __builtin_fmaf(f, s1 - s0, s0);
+    if (CHECK)
+        v = (t >= e.lo && t <= e.hi) ? v : 0.f;     // outside [0, S-1]: no contribution
+    return v;
+}
+
+// y^1 .. y^K of the signed K-th root of v.
+template <int K>
+__device__ __forceinline__ void powers(float v, float (&T)[K])
+{
+    const float a = __builtin_fabsf(v);
+    if constexpr (K == 1) {
+        T[0] = v;
+    } else if constexpr (K == 2) {
+        float r = __builtin_amdgcn_sqrtf(a);
+        T[0] = __builtin_copysignf(r, v);
+        T[1] = a;
+    } else if constexpr (K == 4) {
+        float r2 = __builtin_amdgcn_sqrtf(a);
+        float r = __builtin_amdgcn_sqrtf(r2);
+        T[0] = __builtin_copysignf(r, v);
+        T[1] = r2;
+        T[2] = T[0] * r2;
+        T[3] = a;
+    } else {
+        // |v|^(1/K) = 2^(log2|v| / K); v = 0 gives 2^-inf = 0
+        float r = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(a) * (1.0f / K));
+        float r2 = r * r;
+        T[0] = __builtin_copysignf(r, v);
+        T[1] = r2;
+        T[2] = T[0] * r2;
+        if constexpr (K == 3) {
+            T[2] = v;
+        } else {
+            T[3] = r2 * r2;
+            if constexpr (K == 5) {
+                T[4] = v;
+            } else {
+                T[4] = T[2] * r2;
+                T[5] = a;
+            }
+        }
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, int nch, int window,
+                                            float* __restrict__ lds, int wave, int lane)
+{
+    using T = typename Storage<DT>::T;
+    const T* __restrict__ rf = static_cast<const T*>(A.rf);
+    for (int base = 0; base < window; base += 64) {
+        const int i = base + lane;
+        int c = wave;
+        // four channels per pass so four loads are in flight per lane
+        for (; c + 12 < nch; c += 16) {
+            float v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const hodmas_stage_entry se = st[c + 4 * m];
+                const int t = se.first_sample + i;
+                v[m] = 0.f;
+                if (i < window && t >= 0 && t < A.n_samples)
+                    v[m] = widen(rf[(int64_t)se.channel * A.stride + t]) * A.in_scale;
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (i < window)
+                    lds[(c + 4 * m) * window + i] = v[m];
+        }
+        for (; c < nch; c += 4) {
+            const hodmas_stage_entry se = st[c];
+            const int t = se.first_sample + i;
+            float v = 0.f;
+            if (i < window && t >= 0 && t < A.n_samples)
+                v = widen(rf[(int64_t)se.channel * A.stride + t]) * A.in_scale;
+            if (i < window)
+                lds[c * window + i] = v;
+        }
+    }
+}
+
+template <int K, bool COMP, bool CHECK>
+__device__ __forceinline__ void accumulate_chunk(ConstEntry E, int nch, int g, int split, float u2,
+                                                 float q, const float* __restrict__ lds,
+                                                 float (&s)[K], float (&c)[K])
+{
+    int sl = g;
+    for (; sl + 3 * split < nch; sl += 4 * split) {
+        float T[4][K];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const hodmas_chan_entry e = E[sl + m * split];
+            powers<K>(gather<CHECK>(e, u2, q, lds), T[m]);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (COMP) {
+                // pairwise over the four elements, then one Kahan step
+                kahan_add(s[j], c[j], (T[0][j] + T[1][j]) + (T[2][j] + T[3][j]));
+            } else {
+                s[j] += T[0][j];
+                s[j] += T[1][j];
+                s[j] += T[2][j];
+                s[j] += T[3][j];
+            }
+        }
+    }
+    for (; sl < nch; sl += split) {
+        float T[K];
+        const hodmas_chan_entry e = E[sl];
+        powers<K>(gather<CHECK>(e, u2, q, lds), T);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (COMP)
+                kahan_add(s[j], c[j], T[j]);
+            else
+                s[j] += T[j];
+        }
+    }
+}
+
+// Newton's identities: e_m = (1/m) sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
+template <int K, typename R>
+__device__ __forceinline__ R newton(const R (&p)[K])
+{
+    R e[K + 1];
+    e[0] = R(1);
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+        R acc = R(0);
+#pragma unroll
+        for (int j = 1; j <= m; ++j) {
+            R term = e[m - j] * p[j - 1];
+            acc = (j & 1) ? acc + term : acc - term;
+        }
+        e[m] = acc * (R(1) / R(m));
+    }
+    return e[K];
+}
+
+template <int K, int DT, bool COMP>
+__global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
+{
+    extern __shared__ float lds[];
+    const int tile = blockIdx.x;
+    const hodmas_tile_desc td = ConstTile(A.tiles)[tile];
+    const int tid = threadIdx.x;
+    const int npix = kBlock / A.split;
+    const int g = __builtin_amdgcn_readfirstlane(tid / npix);   // npix is a multiple of 64
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int pl = tid - g * npix;
+    const int lx = pl % A.tile_x, lz = pl / A.tile_x;
+    const bool valid = lx < td.nx && lz < td.nz;
+    const int ix = td.ix0 + min(lx, td.nx - 1);
+    const int iz = td.iz0 + min(lz, td.nz - 1);
+
+    if (td.n_active < K) {
+        // fewer contributing elements than the order: no K-subset exists, e_K = 0 exactly
+        if (g == 0 && valid)
+            A.image[(int64_t)iz * A.nx + ix] = 0.f;
+        return;
+    }
+
+    // pixel offset from the anchor, in float64 once per pixel
+    const double u = A.x0s + ix * A.dxs - td.xa;
+    const double w = A.z0s + iz * A.dzs - td.za;
+    const float u2 = (float)(2.0 * u);
+    const float q = (float)(u * u + w * (w + 2.0 * td.za));
+
+    float s[K], c[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        s[j] = 0.f;
+        c[j] = 0.f;
+    }
+    ConstEntry E = ConstEntry(A.entries) + td.first_entry;
+    ConstStage St = ConstStage(A.stage) + td.first_entry;
+    for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
+        const int nch = min(A.chunk, td.n_active - c0);
+        __syncthreads();
+        stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, lane);
+        __syncthreads();
+        if (td.check)
+            accumulate_chunk<K, COMP, true>(E + c0, nch, g, A.split, u2, q, lds, s, c);
+        else
+            accumulate_chunk<K, COMP, false>(E + c0, nch, g, A.split, u2, q, lds, s, c);
+    }
+
+    if (A.split > 1) {
+        // fixed-order combination of the groups' partial sums through LDS
+        __syncthreads();
+        float* red = lds;
+        if (g > 0) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                red[((g - 1) * npix + pl) * 2 * K + 2 * j] = s[j];
+                red[((g - 1) * npix + pl) * 2 * K + 2 * j + 1] = c[j];
+            }
+        }
+        __syncthreads();
+        if (g == 0) {
+            for (int gg = 1; gg < A.split; ++gg) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const float so = red[((gg - 1) * npix + pl) * 2 * K + 2 * j];
+                    const float co = red[((gg - 1) * npix + pl) * 2 * K + 2 * j + 1];
+                    if (COMP) {
+                        kahan_add(s[j], c[j], so);
+                        kahan_add(s[j], c[j], -co);
+                    } else {
+                        s[j] += so;
+                    }
+                }
+            }
+        }
+    }
+    if (g != 0 || !valid)
+        return;
+    using R = typename std::conditional<(K >= 5), double, float>::type;
+    R p[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        p[j] = COMP ? R(s[j]) - R(c[j]) : R(s[j]);
+    const R ek = newton<K, R>(p);
+    A.image[(int64_t)iz * A.nx + ix] = (float)(ek * R(A.out_scale));
+}
+
+template <int K, int DT>
+int launch_k(const FrameArgs& a, bool comp, int64_t lds_bytes, hipStream_t st)
+{
+    dim3 grid(a.n_tiles), block(kBlock);
+    if (comp)
+        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true>), grid, block, (size_t)lds_bytes, st, a);
+    else
+        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, false>), grid, block, (size_t)lds_bytes, st, a);
+    return (int)hipGetLastError();
+}
+
+template <int DT>
+int launch_dt(const FrameArgs& a, int order, bool comp, int64_t lds_bytes, hipStream_t st)
+{
+    switch (order) {
+    case 1: return launch_k<1, DT>(a, comp, lds_bytes, st);
+    case 2: return launch_k<2, DT>(a, comp, lds_bytes, st);
+    case 3: return launch_k<3, DT>(a, comp, lds_bytes, st);
+    case 4: return launch_k<4, DT>(a, comp, lds_bytes, st);
+    case 5: return launch_k<5, DT>(a, comp, lds_bytes, st);
+    case 6: return launch_k<6, DT>(a, comp, lds_bytes, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, int64_t lds_bytes,
+                 void* stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (dtype) {
+    case HODMAS_F32: return launch_dt<HODMAS_F32>(a, order, compensated, lds_bytes, st);
+    case HODMAS_F16: return launch_dt<HODMAS_F16>(a, order, compensated, lds_bytes, st);
+    case HODMAS_I16: return launch_dt<HODMAS_I16>(a, order, compensated, lds_bytes, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
+}  // namespace hodmas

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of ``libhodmas.so`` (declared in ``include/hodmas.h``).
+
+Argument marshalling only: every step of the beamforming runs in the HIP
+library.  Device memory and streams come from PyTorch (``torch.Tensor`` on a
+ROCm device, ``torch.cuda.Stream``); nothing here computes image values.
+If the library is missing this module raises on import -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhodmas.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = range(6)
+F32, F16, I16 = 0, 1, 2
+MAX_ORDER = 6
+FLAG_ACC_PLAIN = 0x1
+FLAG_HOST_ONLY = 0x2
+FLAG_FORCE_CHECK = 0x4
+
+_DTYPE_NAMES = {"f32": F32, "f16": F16, "i16": I16, "float32": F32, "float16": F16, "int16": I16}
+
+
+class HodmasError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_elements", ctypes.c_int32), ("pitch_m", ctypes.c_double),
+                ("sound_speed_m_s", ctypes.c_double), ("fs_hz", ctypes.c_double),
+                ("t0_s", ctypes.c_double), ("element_x_m", ctypes.POINTER(ctypes.c_double))]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("x0_m", ctypes.c_double),
+                ("dx_m", ctypes.c_double), ("z0_m", ctypes.c_double), ("dz_m", ctypes.c_double)]
+
+
+class RfDesc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("channel_stride", ctypes.c_int64), ("dequant_scale", ctypes.c_float),
+                ("frame_max", ctypes.c_float)]
+
+
+class Tiling(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_elements", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("max_order", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("tiling", Tiling), ("n_tiles", ctypes.c_int32), ("max_window", ctypes.c_int32),
+                ("active_pairs", ctypes.c_int64), ("lds_bytes", ctypes.c_int64),
+                ("table_bytes", ctypes.c_int64), ("flags", ctypes.c_uint32)]
+
+
+class TileDesc(ctypes.Structure):
+    _fields_ = [("ix0", ctypes.c_int32), ("iz0", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("n_active", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("check", ctypes.c_int32), ("first_entry", ctypes.c_int32),
+                ("xa", ctypes.c_double), ("za", ctypes.c_double)]
+
+
+class ChanEntry(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_float), ("d0sq", ctypes.c_float), ("d0", ctypes.c_float),
+                ("frac0", ctypes.c_float), ("lo", ctypes.c_float), ("hi", ctypes.c_float),
+                ("off", ctypes.c_int32), ("channel", ctypes.c_int32)]
+
+
+class StageEntry(ctypes.Structure):
+    _fields_ = [("channel", ctypes.c_int32), ("first_sample", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhodmas.so is not built (run __graft_entry__.build() or "
+                          "python paper_2203_14906_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+    L.hodmas_plan.restype = i32
+    L.hodmas_plan.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Grid), ctypes.POINTER(RfDesc),
+                              i32, u32, ctypes.POINTER(Tiling), ctypes.POINTER(vp)]
+    L.hodmas_beamform.restype = i32
+    L.hodmas_beamform.argtypes = [vp, vp, i32, vp, vp]
+    L.hodmas_destroy.restype = i32
+    L.hodmas_destroy.argtypes = [vp]
+    L.hodmas_status_string.restype = ctypes.c_char_p
+    L.hodmas_status_string.argtypes = [i32]
+    L.hodmas_plan_get_info.restype = i32
+    L.hodmas_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.hodmas_plan_tables.restype = i32
+    L.hodmas_plan_tables.argtypes = [vp, ctypes.POINTER(ctypes.POINTER(TileDesc)),
+                                     ctypes.POINTER(ctypes.POINTER(ChanEntry)),
+                                     ctypes.POINTER(ctypes.POINTER(StageEntry)),
+                                     ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
+    L.hodmas_version.restype = ctypes.c_char_p
+    L.hodmas_version.argtypes = []
+    return L
+
+
+lib = _load()
+
+
+def status_string(status: int) -> str:
+    return lib.hodmas_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return lib.hodmas_version().decode()
+
+
+def _check(status, what):
+    if status != OK:
+        raise HodmasError(status, what)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A resident plan: geometry, grid, RF layout and the device delay tables."""
+
+    def __init__(self, geometry, grid, n_samples, dtype="f32", *, max_order=MAX_ORDER,
+                 dequant_scale=1.0, frame_max=0.0, channel_stride=None, flags=0, tiling=None):
+        self.n_elements = int(geometry.n_elements)
+        self.n_samples = int(n_samples)
+        self.nx, self.nz = int(grid.nx), int(grid.nz)
+        self.dtype = _DTYPE_NAMES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.channel_stride = int(channel_stride if channel_stride is not None else n_samples)
+        self.max_order = int(max_order)
+        ex = getattr(geometry, "element_x_m", None)
+        self._ex = None
+        g = Geometry(self.n_elements, float(geometry.pitch_m), float(geometry.sound_speed_m_s),
+                     float(geometry.fs_hz), float(geometry.t0_s), None)
+        if ex is not None:
+            self._ex = (ctypes.c_double * self.n_elements)(*[float(v) for v in ex])
+            g.element_x_m = ctypes.cast(self._ex, ctypes.POINTER(ctypes.c_double))
+        gr = Grid(self.nx, self.nz, float(grid.x0_m), float(grid.dx_m), float(grid.z0_m),
+                  float(grid.dz_m))
+        rd = RfDesc(self.dtype, self.n_samples, self.channel_stride, float(dequant_scale),
+                    float(frame_max))
+        til = None
+        if tiling is not None:
+            til = ctypes.byref(Tiling(*[int(v) for v in tiling]))
+        handle = ctypes.c_void_p()
+        _check(lib.hodmas_plan(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), self.max_order,
+                               int(flags), til, ctypes.byref(handle)), "hodmas_plan")
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> PlanInfo:
+        inf = PlanInfo()
+        _check(lib.hodmas_plan_get_info(self._h, ctypes.byref(inf)), "hodmas_plan_get_info")
+        return inf
+
+    def tables(self):
+        """Host copies of the plan tables as lists of ctypes records."""
+        t = ctypes.POINTER(TileDesc)()
+        e = ctypes.POINTER(ChanEntry)()
+        s = ctypes.POINTER(StageEntry)()
+        nt, ne = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.hodmas_plan_tables(self._h, ctypes.byref(t), ctypes.byref(e), ctypes.byref(s),
+                                      ctypes.byref(nt), ctypes.byref(ne)), "hodmas_plan_tables")
+        return t[:nt.value], e[:ne.value], s[:ne.value]
+
+    def beamform(self, rf, order, out=None, stream=None):
+        """Beamform ``rf`` (device tensor [N][stride] of the plan's dtype) at
+        ``order`` into ``out`` (device float32 [nz][nx]); returns ``out``."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nz, self.nx), dtype=torch.float32, device=rf.device)
+        _check_tensor(rf, self)
+        if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != self.nx * self.nz:
+            raise ValueError("out must be a contiguous float32 tensor of nz*nx elements")
+        if not out.is_cuda:
+            raise ValueError("out must live on the GPU")
+        _check(lib.hodmas_beamform(self._h, ctypes.c_void_p(rf.data_ptr()), int(order),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+               "hodmas_beamform")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.hodmas_destroy(self._h)
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_TORCH_DT = {F32: "float32", F16: "float16", I16: "int16"}
+
+
+def _check_tensor(rf, plan):
+    import torch
+    if not rf.is_cuda:
+        raise ValueError("rf must live on the GPU")
+    if str(rf.dtype).split(".")[-1] != _TORCH_DT[plan.dtype]:
+        raise ValueError("rf dtype %s does not match the plan (%s)" % (rf.dtype, _TORCH_DT[plan.dtype]))
+    if rf.dim() != 2 or rf.shape[0] != plan.n_elements or rf.stride(1) != 1 or \
+            rf.stride(0) != plan.channel_stride or rf.shape[1] < plan.n_samples:
+        raise ValueError("rf must be [n_elements][>= n_samples] with row stride %d" % plan.channel_stride)
+    return torch

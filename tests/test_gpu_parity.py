@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Tolerances (relative L2 over the compared pixels):
+1e-5 for float32 storage; 2e-3 for float16 / int16 storage, where the oracle is
+fed the same stored values (widened exactly) -- the kernel's own arithmetic is
+additionally held to 2e-5 there."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2203_14906_amd import phantom as ph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+TOL_REDUCED = 2e-3
+TOL_SAME_VALUES = 2e-5
+
+
+@pytest.fixture(scope="module")
+def hd():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2203_14906_amd import hodmas          # raises if libhodmas.so is missing
+    return hodmas
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(g, o):
+    n = np.linalg.norm(o)
+    return np.linalg.norm(g - o) / n if n > 0 else np.linalg.norm(g)
+
+
+def stored(rf, dtype, seed=0):
+    """(stored array, dequant scale) for a storage form."""
+    if dtype == "f32":
+        return ph.to_fp32(rf), 1.0
+    if dtype == "f16":
+        return ph.to_fp16(rf), 1.0
+    codes, scale = ph.to_int16(rf, seed)
+    return codes, float(scale)
+
+
+def gpu_image(hd, plan, arr, order):
+    dev = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    out = plan.beamform(dev, order)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def oracle_image(arr, scale, geom, grid, order, pixels=None):
+    return O.beamform(arr, geom, grid, order, dequant_scale=scale if arr.dtype == np.int16 else None,
+                      pixels=pixels)
+
+
+def check(err, dtype, what):
+    say("%-48s rel L2 %.3e" % (what, err))
+    if dtype == "f32":
+        assert err <= TOL_F32, what
+    else:
+        assert err <= TOL_REDUCED, what
+        assert err <= TOL_SAME_VALUES, what
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_config_full_image_fp32(hd, cfg):
+    f = ph.config_frame(cfg)
+    orders = ph.CONFIGS[cfg]["orders"]
+    arr = ph.to_fp32(f.rf)
+    plan = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=max(orders))
+    say("config %d: %d x %d grid, N=%d, S=%d, tiling %s" % (cfg, f.grid.nx, f.grid.nz, arr.shape[0],
+        arr.shape[1], tuple(getattr(plan.info().tiling, n) for n in ("tile_x", "tile_z", "split", "chunk"))))
+    for k in orders:
+        say("config %d order %d" % (cfg, k))
+        g = gpu_image(hd, plan, arr, k)
+        o = oracle_image(arr, 1.0, f.geometry, f.grid, k)
+        check(rel_l2(g, o), "f32", "config %d f32 order %d" % (cfg, k))
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["i16", "f16"])
+def test_config3_sampled(hd, dtype):
+    f = ph.config_frame(3)
+    arr, scale = stored(f.rf, dtype, seed=3000)
+    plan = hd.Plan(f.geometry, f.grid, arr.shape[1], dtype, max_order=6, dequant_scale=scale)
+    rng = np.random.default_rng(33)
+    n = 3000
+    ix = np.concatenate([rng.integers(0, 1024, n), np.arange(1024), [0, 1023, 0, 1023]]).astype(np.int32)
+    iz = np.concatenate([rng.integers(0, 1024, n), np.full(1024, 1023), [0, 0, 1023, 1023]]).astype(np.int32)
+    for k in range(1, 7):
+        say("config 3 %s order %d" % (dtype, k))
+        g = gpu_image(hd, plan, arr, k)
+        o = oracle_image(arr, scale, f.geometry, f.grid, k, pixels=(ix, iz))
+        check(rel_l2(g[iz, ix], o), dtype, "config 3 %s order %d (sampled)" % (dtype, k))
+    plan.close()
+
+
+def test_config3_full_image_order6_f16(hd):
+    f = ph.config_frame(3)
+    arr, scale = stored(f.rf, "f16")
+    plan = hd.Plan(f.geometry, f.grid, arr.shape[1], "f16", max_order=6)
+    say("config 3 f16 order 6, full image")
+    g = gpu_image(hd, plan, arr, 6)
+    o = oracle_image(arr, 1.0, f.geometry, f.grid, 6)
+    check(rel_l2(g, o), "f16", "config 3 f16 order 6 (full image)")
+    plan.close()
+
+
+@pytest.mark.parametrize("tiling", [None, (16, 16, 1, 64), (16, 8, 2, 5), (8, 8, 4, 3), (32, 8, 1, 7)])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "i16"])
+def test_small_ragged_frames(hd, tiling, dtype):
+    # several tiles plus ragged edges; a deep grid so far pixels run past the record
+    f = ph.make_frame(13, 300, 37, 53, n_points=6, n_lines=1, snr_db=15.0, seed=17)
+    grid = ph.Grid(nx=37, nz=53, x0_m=-3e-3, dx_m=0.17e-3, z0_m=0.2e-3, dz_m=0.21e-3)
+    arr, scale = stored(f.rf, dtype, seed=17)
+    plan = hd.Plan(f.geometry, grid, arr.shape[1], dtype, max_order=6, dequant_scale=scale,
+                   tiling=tiling)
+    for k in range(1, 7):
+        say("small frame %s tiling %s order %d" % (dtype, tiling, k))
+        g = gpu_image(hd, plan, arr, k)
+        o = oracle_image(arr, scale, f.geometry, grid, k)
+        check(rel_l2(g, o), dtype, "small %s %s k=%d" % (dtype, tiling, k))
+    plan.close()
+
+
+def test_single_element_and_order_above_n(hd):
+    f = ph.make_frame(1, 256, 9, 11, n_points=2, seed=4)
+    grid = ph.make_grid(9, 11, 3e-3, 5e-3)
+    arr = ph.to_fp32(f.rf)
+    plan = hd.Plan(f.geometry, grid, 256, "f32", max_order=6)
+    o1 = oracle_image(arr, 1.0, f.geometry, grid, 1)
+    assert rel_l2(gpu_image(hd, plan, arr, 1), o1) <= TOL_F32
+    for k in range(2, 7):                       # k > N: no k-subset exists
+        assert np.all(gpu_image(hd, plan, arr, k) == 0.0)
+    plan.close()
+
+
+def test_zero_rf_and_out_of_record(hd):
+    g = ph.Geometry(16)
+    grid = ph.make_grid(20, 20, 4.8e-3, 5e-3)
+    plan = hd.Plan(g, grid, 128, "f32", max_order=6)
+    zero = np.zeros((16, 128), dtype=np.float32)
+    for k in range(1, 7):
+        assert np.all(gpu_image(hd, plan, zero, k) == 0.0)
+    plan.close()
+    # a grid 40 mm deep sees nothing of a 128-sample record
+    far = ph.Grid(nx=8, nz=8, x0_m=-1e-3, dx_m=0.3e-3, z0_m=40e-3, dz_m=0.3e-3)
+    plan = hd.Plan(g, far, 128, "f32", max_order=3)
+    assert plan.info().active_pairs == 0
+    ones = np.ones((16, 128), dtype=np.float32)
+    for k in (1, 2, 3):
+        assert np.all(gpu_image(hd, plan, ones, k) == 0.0)
+    plan.close()
+
+
+def test_t0_irregular_stride_and_scale(hd):
+    rng = np.random.default_rng(21)
+    ex = np.sort(rng.uniform(-4e-3, 4e-3, 29))
+    geom = ph.Geometry(29, t0_s=1.5e-6, element_x_m=ex)
+    grid = ph.Grid(nx=45, nz=31, x0_m=-4.5e-3, dx_m=0.2e-3, z0_m=0.3e-3, dz_m=0.25e-3)
+    S, stride = 500, 517
+    rf = rng.standard_normal((29, S)) * 0.3
+    padded = np.full((29, stride), np.nan, dtype=np.float32)   # padding must never be read
+    padded[:, :S] = rf
+    plan = hd.Plan(geom, grid, S, "f32", max_order=6, channel_stride=stride, frame_max=2.5)
+    for k in range(1, 7):
+        dev = torch.from_numpy(padded).cuda()
+        got = plan.beamform(dev, k).cpu().numpy().astype(np.float64)
+        o = O.beamform(padded[:, :S].copy(), geom, grid, k)
+        check(rel_l2(got, o), "f32", "t0/irregular/stride k=%d" % k)
+    plan.close()
+
+
+def test_plain_and_forced_check_modes(hd):
+    f = ph.make_frame(24, 400, 33, 29, n_points=5, n_lines=1, seed=8)
+    arr = ph.to_fp32(f.rf)
+    base = hd.Plan(f.geometry, f.grid, 400, "f32", max_order=6)
+    forced = hd.Plan(f.geometry, f.grid, 400, "f32", max_order=6, flags=hd.FLAG_FORCE_CHECK)
+    plain = hd.Plan(f.geometry, f.grid, 400, "f32", max_order=6, flags=hd.FLAG_ACC_PLAIN)
+    for k in range(1, 7):
+        o = oracle_image(arr, 1.0, f.geometry, f.grid, k)
+        a = gpu_image(hd, base, arr, k)
+        np.testing.assert_array_equal(gpu_image(hd, forced, arr, k), a)
+        check(rel_l2(gpu_image(hd, plain, arr, k), o), "f32", "plain accumulation k=%d" % k)
+        check(rel_l2(a, o), "f32", "compensated k=%d" % k)
+    for p in (base, forced, plain):
+        p.close()
+
+
+def test_repeatable_bitwise(hd):
+    f = ph.config_frame(1)
+    arr = ph.to_fp32(f.rf)
+    plan = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6)
+    dev = torch.from_numpy(arr).cuda()
+    for k in (1, 4, 6):
+        first = plan.beamform(dev, k).clone()
+        for _ in range(3):
+            assert torch.equal(plan.beamform(dev, k), first)
+    plan.close()
+
+
+def test_abi_errors_on_device(hd):
+    f = ph.make_frame(8, 128, 8, 8, n_points=1, seed=2)
+    plan = hd.Plan(f.geometry, f.grid, 128, "f32", max_order=4)
+    dev = torch.from_numpy(ph.to_fp32(f.rf)).cuda()
+    out = torch.empty((8, 8), dtype=torch.float32, device="cuda")
+    L = hd.lib
+    p_rf, p_out = ctypes.c_void_p(dev.data_ptr()), ctypes.c_void_p(out.data_ptr())
+    for k in (0, 5, 7, -1):
+        assert L.hodmas_beamform(plan.handle, p_rf, k, p_out, None) == hd.EUNSUPPORTED
+    assert L.hodmas_beamform(plan.handle, None, 1, p_out, None) == hd.EINVAL
+    assert L.hodmas_beamform(plan.handle, p_rf, 1, None, None) == hd.EINVAL
+    assert L.hodmas_beamform(plan.handle, p_rf, 4, p_out, None) == hd.OK
+    torch.cuda.synchronize()
+    with pytest.raises(ValueError):
+        plan.beamform(dev.to(torch.float16), 1)
+    plan.close()
+
+
+def test_streams_and_concurrent_plans(hd):
+    f1 = ph.make_frame(32, 512, 48, 40, n_points=3, seed=31)
+    f2 = ph.make_frame(64, 1024, 40, 64, n_points=3, seed=32)
+    a1, a2 = ph.to_fp32(f1.rf), ph.to_fp32(f2.rf)
+    p1 = hd.Plan(f1.geometry, f1.grid, 512, "f32", max_order=6)
+    p2 = hd.Plan(f2.geometry, f2.grid, 1024, "f32", max_order=6)
+    d1, d2 = torch.from_numpy(a1).cuda(), torch.from_numpy(a2).cuda()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    outs = []
+    for k in (2, 5):
+        with torch.cuda.stream(s1):
+            o1 = p1.beamform(d1, k, stream=s1)
+        with torch.cuda.stream(s2):
+            o2 = p2.beamform(d2, k, stream=s2)
+        outs.append((k, o1, o2))
+    torch.cuda.synchronize()
+    for k, o1, o2 in outs:
+        check(rel_l2(o1.cpu().numpy().astype(np.float64), oracle_image(a1, 1.0, f1.geometry, f1.grid, k)),
+              "f32", "stream 1 k=%d" % k)
+        check(rel_l2(o2.cpu().numpy().astype(np.float64), oracle_image(a2, 1.0, f2.geometry, f2.grid, k)),
+              "f32", "stream 2 k=%d" % k)
+    p1.close()
+    p2.close()
+
+
+def test_maximum_sizes(hd):
+    # the element-count limit, a long record and the widest grid side of this build
+    cases = [
+        (4096, 2048, 0.01e-3, ph.Grid(nx=16, nz=8, x0_m=-2.4e-3, dx_m=0.3e-3, z0_m=5e-3, dz_m=0.3e-3)),
+        (8, 1 << 20, 0.3e-3, ph.Grid(nx=24, nz=16, x0_m=-1e-3, dx_m=0.1e-3, z0_m=10.0, dz_m=1e-3)),
+        (8, 512, 0.3e-3, ph.Grid(nx=16384, nz=4, x0_m=-8e-3, dx_m=1e-6, z0_m=2e-3, dz_m=1e-3)),
+    ]
+    rng = np.random.default_rng(99)
+    for n, S, pitch, grid in cases:
+        geom = ph.Geometry(n, pitch_m=pitch)
+        arr = rng.standard_normal((n, S)).astype(np.float32)
+        plan = hd.Plan(geom, grid, S, "f32", max_order=6)
+        for k in (1, 3, 6):
+            say("max-size case N=%d S=%d grid %dx%d order %d" % (n, S, grid.nx, grid.nz, k))
+            g = gpu_image(hd, plan, arr, k)
+            o = oracle_image(arr, 1.0, geom, grid, k)
+            check(rel_l2(g, o), "f32", "max N=%d S=%d nx=%d k=%d" % (n, S, grid.nx, k))
+        plan.close()

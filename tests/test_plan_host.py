@@ -1,0 +1,164 @@
+"""Host logic of the plan (no GPU): argument validation and the float64 tables
+(delay anchors, LDS windows, skipped elements) checked against exact delays."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_2203_14906_amd import hodmas, phantom as ph
+
+C, FS = 1540.0, 40e6
+LAM = C / FS
+
+
+def _plan(geom, grid, S, dtype="f32", **kw):
+    kw.setdefault("flags", 0)
+    kw["flags"] |= hodmas.FLAG_HOST_ONLY
+    return hodmas.Plan(geom, grid, S, dtype, **kw)
+
+
+def _status(fn):
+    with pytest.raises(hodmas.HodmasError) as ei:
+        fn()
+    return ei.value.status
+
+
+def test_argument_validation():
+    g = ph.Geometry(16)
+    grid = ph.make_grid(20, 20, 16 * 0.3e-3, 5e-3)
+    ok = _plan(g, grid, 256)
+    ok.close()
+    E = hodmas.EINVAL
+    assert _status(lambda: _plan(ph.Geometry(0), grid, 256)) == E
+    assert _status(lambda: _plan(ph.Geometry(16, sound_speed_m_s=0.0), grid, 256)) == E
+    assert _status(lambda: _plan(ph.Geometry(16, fs_hz=float("nan")), grid, 256)) == E
+    assert _status(lambda: _plan(ph.Geometry(16, pitch_m=-1.0), grid, 256)) == E
+    assert _status(lambda: _plan(ph.Geometry(16, element_x_m=[0.0] * 15 + [float("inf")]), grid, 256)) == E
+    assert _status(lambda: _plan(g, ph.Grid(0, 4, 0.0, 1e-4, 1e-3, 1e-4), 256)) == E
+    assert _status(lambda: _plan(g, ph.Grid(4, 4, 0.0, -1e-4, 1e-3, 1e-4), 256)) == E
+    assert _status(lambda: _plan(g, ph.Grid(4, 4, 0.0, 1e-4, 0.0, 1e-4), 256)) == E      # z0 = 0
+    assert _status(lambda: _plan(g, ph.Grid(4, 4, 0.0, 1e-4, 1e-3, 0.0), 256)) == E
+    assert _status(lambda: _plan(g, ph.Grid(16385, 4, 0.0, 1e-4, 1e-3, 1e-4), 256)) == E
+    assert _status(lambda: _plan(g, grid, 0)) == E
+    assert _status(lambda: _plan(g, grid, 256, channel_stride=255)) == E
+    assert _status(lambda: _plan(g, grid, 256, dtype=7)) == E
+    assert _status(lambda: _plan(g, grid, 256, "i16", dequant_scale=0.0)) == E
+    assert _status(lambda: _plan(g, grid, 256, frame_max=-1.0)) == E
+    assert _status(lambda: _plan(g, grid, 256, max_order=0)) == E
+    assert _status(lambda: _plan(g, grid, 256, max_order=7)) == E
+    assert _status(lambda: _plan(g, grid, 256, tiling=(16, 16, 3, 64))) == E
+    assert _status(lambda: _plan(g, grid, 256, tiling=(16, 8, 1, 64))) == E
+    # delays beyond float32's exact-integer range are refused
+    assert _status(lambda: _plan(g, ph.Grid(4, 4, 0.0, 1e-4, 1e4, 1e-4), 256)) == E
+
+
+def test_null_pointers_and_destroy():
+    L = hodmas.lib
+    out = ctypes.c_void_p()
+    assert L.hodmas_plan(None, None, None, 1, 0, None, ctypes.byref(out)) == hodmas.EINVAL
+    assert L.hodmas_destroy(None) == hodmas.OK
+    assert L.hodmas_beamform(None, None, 1, None, None) == hodmas.EINVAL
+    p = _plan(ph.Geometry(8), ph.make_grid(8, 8, 2.4e-3, 3e-3), 128)
+    # a host-only plan has no device tables to launch with
+    assert L.hodmas_beamform(p.handle, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None) == hodmas.EINVAL
+    assert L.hodmas_plan_get_info(p.handle, None) == hodmas.EINVAL
+    p.close()
+
+
+def _exact_delays(ex, grid, t0s, ix, iz):
+    xp = (grid.x0_m + ix * grid.dx_m) / LAM
+    zp = (grid.z0_m + iz * grid.dz_m) / LAM
+    return np.sqrt((xp[:, None] - ex[None, :] / LAM) ** 2 + zp[:, None] ** 2) - t0s
+
+
+def _f32(x):
+    return np.float32(x)
+
+
+@pytest.mark.parametrize("case", ["deep", "shallow_t0", "irregular", "coarse"])
+def test_tables_cover_every_delay(case):
+    S = 400
+    if case == "deep":           # far corners run past the record: skips and checks
+        g = ph.Geometry(24)
+        grid = ph.make_grid(41, 37, 24 * 0.3e-3 * 3, 20e-3)
+        tiling = (16, 16, 1, 8)
+    elif case == "shallow_t0":   # t0 pushes near pixels before the record start
+        g = ph.Geometry(16, t0_s=2e-6)
+        grid = ph.make_grid(30, 50, 16 * 0.3e-3, 8e-3)
+        tiling = (16, 8, 2, 5)
+    elif case == "irregular":    # non-uniform element positions, ragged tiles
+        rng = np.random.default_rng(3)
+        g = ph.Geometry(13, element_x_m=np.sort(rng.uniform(-3e-3, 3e-3, 13)))
+        grid = ph.Grid(nx=19, nz=23, x0_m=-2e-3, dx_m=0.21e-3, z0_m=0.5e-3, dz_m=0.33e-3)
+        tiling = (8, 8, 4, 3)
+    else:                        # coarse pixels: long windows
+        g = ph.Geometry(32)
+        grid = ph.make_grid(24, 24, 32 * 0.3e-3, 12e-3)
+        tiling = (16, 16, 1, 64)
+    plan = _plan(g, grid, S, tiling=tiling)
+    info = plan.info()
+    tiles, entries, stage = plan.tables()
+    ex = g.positions()
+    t0s = g.t0_s * FS
+    chunk = info.tiling.chunk
+    covered = np.zeros((grid.nz, grid.nx), dtype=int)
+    n_checked_tiles = 0
+    for td in tiles:
+        covered[td.iz0:td.iz0 + td.nz, td.ix0:td.ix0 + td.nx] += 1
+        ixs, izs = np.meshgrid(np.arange(td.ix0, td.ix0 + td.nx), np.arange(td.iz0, td.iz0 + td.nz))
+        ixs, izs = ixs.ravel(), izs.ravel()
+        t = _exact_delays(ex, grid, t0s, ixs, izs)                     # [pixels, elements]
+        active = [e.channel for e in entries[td.first_entry:td.first_entry + td.n_active]]
+        for i in range(len(ex)):
+            if i not in active:                                        # skipped: never in the record
+                assert np.all((t[:, i] < 0) | (t[:, i] > S - 1)), (td.ix0, td.iz0, i)
+        if not td.check:
+            assert np.all(t[:, active] >= 0.5) and np.all(t[:, active] <= S - 1.5)
+        else:
+            n_checked_tiles += 1
+        assert td.window <= info.max_window
+        ia, ja = td.ix0 + (td.nx - 1) // 2, td.iz0 + (td.nz - 1) // 2
+        assert td.xa == pytest.approx((grid.x0_m + ia * grid.dx_m) / LAM, rel=1e-15)
+        assert td.za == pytest.approx((grid.z0_m + ja * grid.dz_m) / LAM, rel=1e-15)
+        u = (grid.x0_m + ixs * grid.dx_m) / LAM - td.xa
+        w = (grid.z0_m + izs * grid.dz_m) / LAM - td.za
+        u2 = (2.0 * u).astype(np.float32)
+        q = (u * u + w * (w + 2.0 * td.za)).astype(np.float32)
+        for slot in range(td.n_active):
+            e = entries[td.first_entry + slot]
+            st = stage[td.first_entry + slot]
+            i = e.channel
+            assert st.channel == i
+            T0 = int(round(-e.lo))
+            assert e.hi == pytest.approx(S - 1 - T0, abs=0)
+            ta = math.sqrt((td.xa - ex[i] / LAM) ** 2 + td.za ** 2) - t0s
+            assert T0 == math.floor(ta) and e.frac0 == pytest.approx(ta - T0, abs=1e-6)
+            assert e.off == T0 - st.first_sample + (slot % chunk) * td.window
+            # float32 reconstruction of each pixel's delay, as the kernel forms it
+            num = (u2.astype(np.float64) * np.float64(e.a) + q).astype(np.float32)
+            d = np.sqrt(np.abs(np.float64(e.d0sq) + num)).astype(np.float32)
+            r = (1.0 / (d.astype(np.float64) + np.float64(e.d0))).astype(np.float32)
+            trel = (num.astype(np.float64) * r + np.float64(e.frac0)).astype(np.float32)
+            exact = t[:, i] - T0
+            assert np.max(np.abs(trel - exact)) < 1e-3
+            j = np.floor(trel).astype(np.int64) + T0 - st.first_sample     # window position
+            assert j.min() >= 0 and j.max() + 1 <= td.window - 1
+    assert np.all(covered == 1)
+    if case in ("deep", "shallow_t0"):
+        assert n_checked_tiles > 0
+    plan.close()
+
+
+def test_default_tiling_and_info():
+    f = ph.config_frame(2)
+    p = _plan(f.geometry, f.grid, 2048)
+    inf = p.info()
+    assert (inf.tiling.tile_x, inf.tiling.tile_z, inf.tiling.split) == (16, 16, 1)
+    assert inf.n_tiles == 32 * 32
+    assert inf.active_pairs == 32 * 32 * 128           # no element is out of the record here
+    assert inf.lds_bytes == inf.tiling.chunk * inf.max_window * 4
+    small = _plan(ph.config_frame(1).geometry, ph.config_frame(1).grid, 1024)
+    assert small.info().tiling.split in (2, 4)
+    p.close()
+    small.close()
