@@ -190,6 +190,58 @@ hodmas_status hodmas_plan_tables(hodmas_plan_t plan, const hodmas_tile_desc** ti
                                  const hodmas_stage_entry** stage, int32_t* n_tiles,
                                  int64_t* n_entries);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many frames -- each with its own plan, order and storage type --
+ * in one persistent launch.  The library builds a work list of (frame, tile)
+ * units sorted by estimated cost and a fixed grid of workgroups walks it.  Each
+ * tile runs exactly the per-frame code, so every frame's image is bitwise the
+ * same as from hodmas_beamform with its plan, whatever else is in the batch.
+ * A batch object is used from one stream at a time.
+ * ------------------------------------------------------------------------- */
+typedef struct hodmas_batch_s* hodmas_batch_t;
+
+/* Allocate a batch for up to max_frames frames and max_units (frame, tile)
+ * units, on the current HIP device.  max_lds_bytes bounds the LDS any member
+ * plan may need (0: the largest a workgroup can have); it fixes the persistent
+ * grid size.  flags: HODMAS_FLAG_ACC_PLAIN or 0; member plans must match it.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t max_lds_bytes,
+                                  uint32_t flags, hodmas_batch_t* out);
+
+/* Describe the frames of the next launch: frame f is beamformed with plans[f]
+ * at orders[f] from rf[f] (device) into images[f] (device float32 [nz][nx]).
+ * Host arrays of n_frames entries, read during the call.  The work list is
+ * copied to the device asynchronously on `stream` (launches on the same stream
+ * see it).  Errors: EINVAL (null entries, order outside the plan, plan flags,
+ * host-only or other-device plan, too many frames/units, plan LDS above the
+ * batch's bound), EUNSUPPORTED, EDEVICE. */
+hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
+                               const void* const* rf, const int32_t* orders,
+                               float* const* images, int32_t n_frames, void* stream);
+
+/* One persistent launch over the current work list on `stream`. */
+hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
+
+/* Build (once) a HIP graph holding the persistent launch; it reads the work
+ * list from device memory, so later hodmas_batch_set calls need no re-capture.
+ * hodmas_batch_replay launches that graph on `stream`. */
+hodmas_status hodmas_batch_capture(hodmas_batch_t batch);
+hodmas_status hodmas_batch_replay(hodmas_batch_t batch, void* stream);
+
+/* Work-list summary of the last hodmas_batch_set. */
+typedef struct {
+    int32_t n_frames;
+    int64_t n_units;
+    int32_t grid;                /* persistent workgroups */
+    int64_t lds_bytes;           /* dynamic LDS per workgroup */
+    int64_t pixel_channels;      /* sum over frames of nx*nz*N */
+} hodmas_batch_info;
+
+hodmas_status hodmas_batch_get_info(hodmas_batch_t batch, hodmas_batch_info* info);
+
+/* Release the batch (its graph and work-list buffers).  NULL is accepted. */
+hodmas_status hodmas_batch_destroy(hodmas_batch_t batch);
+
 /* Version string of the library. */
 const char* hodmas_version(void);
 

@@ -1,0 +1,283 @@
+// Batched form: a work list of (frame, tile) units over many frames, walked by
+// one persistent launch (optionally replayed from a HIP graph).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "hodmas_internal.h"
+
+using hodmas::BatchFrame;
+using hodmas::BatchHeader;
+using hodmas::BatchUnit;
+
+namespace {
+
+constexpr uint32_t kBatchMagic = 0x48424154u;  // "HBAT"
+constexpr size_t kAlign = 256;
+// Estimated VALU slots per pixel-element by order (delay, gather, root, sums):
+// only used to order the work list, heaviest units first.
+constexpr int64_t kSlots[7] = {0, 19, 25, 32, 32, 36, 38};
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct hodmas_batch_s {
+    uint32_t magic = kBatchMagic;
+    int device = -1;
+    int32_t max_frames = 0;
+    int64_t max_units = 0;
+    int64_t lds_bytes = 0;
+    uint32_t flags = 0;
+    int grid = 0;
+    size_t off_frames = 0, off_units = 0, bytes = 0;
+    char* d_buf = nullptr;
+    char* h_buf = nullptr;           // pinned staging of the work list
+    hipEvent_t copied = nullptr;     // last host->device copy of h_buf
+    bool copy_pending = false;
+    bool has_list = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hodmas_batch_info info{};
+};
+
+namespace {
+
+void release(hodmas_batch_s* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->copied) {
+        (void)hipEventSynchronize(b->copied);
+        (void)hipEventDestroy(b->copied);
+    }
+    if (b->d_buf) (void)hipFree(b->d_buf);
+    if (b->h_buf) (void)hipHostFree(b->h_buf);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->copied = nullptr;
+    b->d_buf = nullptr;
+    b->h_buf = nullptr;
+}
+
+bool valid_batch(const hodmas_batch_s* b) { return b && b->magic == kBatchMagic; }
+
+}  // namespace
+
+extern "C" {
+
+hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t max_lds_bytes,
+                                  uint32_t flags, hodmas_batch_t* out)
+{
+    if (!out)
+        return HODMAS_EINVAL;
+    *out = nullptr;
+    if (max_frames < 1 || max_units < 1 || max_units > (int64_t(1) << 31) || max_lds_bytes < 0 ||
+        max_lds_bytes > hodmas::kMaxLdsBytes || (flags & ~HODMAS_FLAG_ACC_PLAIN))
+        return HODMAS_EINVAL;
+    hodmas_batch_s* b = new (std::nothrow) hodmas_batch_s;
+    if (!b)
+        return HODMAS_ENOMEM;
+    b->max_frames = max_frames;
+    b->max_units = max_units;
+    b->lds_bytes = max_lds_bytes > 0 ? max_lds_bytes : 64 * 1024;
+    b->flags = flags;
+    const bool comp = !(flags & HODMAS_FLAG_ACC_PLAIN);
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&b->device) != hipSuccess || hipGetDeviceProperties(&prop, b->device) != hipSuccess) {
+        delete b;
+        return HODMAS_EDEVICE;
+    }
+    const void* fn = hodmas::batch_kernel(comp);
+    if (b->lds_bytes > 64 * 1024 &&
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return HODMAS_EUNSUPPORTED;
+    }
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)b->lds_bytes) !=
+            hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        delete b;
+        return HODMAS_EUNSUPPORTED;
+    }
+    b->grid = per_cu * prop.multiProcessorCount;
+    b->off_frames = align_up(sizeof(BatchHeader));
+    b->off_units = b->off_frames + align_up(sizeof(BatchFrame) * (size_t)max_frames);
+    b->bytes = b->off_units + align_up(sizeof(BatchUnit) * (size_t)max_units);
+    if (hipMalloc((void**)&b->d_buf, b->bytes) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_buf, b->bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        release(b);
+        delete b;
+        return HODMAS_ENOMEM;
+    }
+    std::memset(b->h_buf, 0, b->bytes);
+    if (hipMemcpy(b->d_buf, b->h_buf, b->bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        release(b);
+        delete b;
+        return HODMAS_EDEVICE;
+    }
+    b->info.grid = b->grid;
+    b->info.lds_bytes = b->lds_bytes;
+    *out = b;
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, const void* const* rf,
+                               const int32_t* orders, float* const* images, int32_t n_frames,
+                               void* stream)
+{
+    if (!valid_batch(b) || !plans || !rf || !orders || !images || n_frames < 1 ||
+        n_frames > b->max_frames)
+        return HODMAS_EINVAL;
+    struct Unit {
+        int64_t cost;
+        int32_t frame, tile;
+    };
+    std::vector<Unit> units;
+    int64_t pixch = 0;
+    try {
+        for (int32_t f = 0; f < n_frames; ++f) {
+            const hodmas_plan_s* p = plans[f];
+            if (!p || p->magic != hodmas::kPlanMagic || !rf[f] || !images[f])
+                return HODMAS_EINVAL;
+            if ((p->flags & HODMAS_FLAG_HOST_ONLY) || p->device != b->device)
+                return HODMAS_EINVAL;
+            if ((p->flags & HODMAS_FLAG_ACC_PLAIN) != (b->flags & HODMAS_FLAG_ACC_PLAIN))
+                return HODMAS_EINVAL;
+            if (orders[f] < 1 || orders[f] > p->max_order)
+                return HODMAS_EUNSUPPORTED;
+            if (p->lds_bytes > b->lds_bytes)
+                return HODMAS_EINVAL;
+            if ((int64_t)(units.size() + p->tiles.size()) > b->max_units)
+                return HODMAS_EINVAL;
+            pixch += int64_t(p->grid.nx) * p->grid.nz * p->geom.n_elements;
+            for (size_t t = 0; t < p->tiles.size(); ++t) {
+                const hodmas_tile_desc& td = p->tiles[t];
+                const int64_t pix = int64_t(td.nx) * td.nz;
+                int64_t cost = pix;  // zero-fill only
+                if (td.n_active >= orders[f])
+                    cost = td.n_active * (pix * kSlots[orders[f]] + int64_t(td.window) * 2);
+                units.push_back(Unit{cost, f, (int32_t)t});
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        return HODMAS_ENOMEM;
+    }
+    std::stable_sort(units.begin(), units.end(),
+                     [](const Unit& x, const Unit& y) { return x.cost > y.cost; });
+    // the pinned staging buffer may still feed the previous asynchronous copy
+    if (b->copy_pending && hipEventSynchronize(b->copied) != hipSuccess)
+        return HODMAS_EDEVICE;
+    b->copy_pending = false;
+    BatchHeader* hdr = reinterpret_cast<BatchHeader*>(b->h_buf);
+    BatchFrame* frames = reinterpret_cast<BatchFrame*>(b->h_buf + b->off_frames);
+    BatchUnit* list = reinterpret_cast<BatchUnit*>(b->h_buf + b->off_units);
+    std::memset(hdr, 0, sizeof(BatchHeader));
+    hdr->n_units = (int32_t)units.size();
+    hdr->n_frames = n_frames;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        std::memset(&frames[f], 0, sizeof(BatchFrame));
+        frames[f].args = hodmas::frame_args(plans[f], rf[f], images[f]);
+        frames[f].order = orders[f];
+        frames[f].dtype = plans[f]->rf.dtype;
+    }
+    for (size_t u = 0; u < units.size(); ++u)
+        list[u] = BatchUnit{units[u].frame, units[u].tile};
+    const size_t used = b->off_units + sizeof(BatchUnit) * units.size();
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(b->d_buf, b->h_buf, used, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(b->copied, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return HODMAS_EDEVICE;
+    }
+    b->copy_pending = true;
+    b->has_list = true;
+    b->info.n_frames = n_frames;
+    b->info.n_units = (int64_t)units.size();
+    b->info.pixel_channels = pixch;
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
+{
+    if (!valid_batch(b) || !b->has_list)
+        return HODMAS_EINVAL;
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(b->d_buf);
+    const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
+    const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
+    int rc = hodmas::launch_batch(hdr, frames, units, b->grid, !(b->flags & HODMAS_FLAG_ACC_PLAIN),
+                                  b->lds_bytes, stream);
+    return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
+}
+
+hodmas_status hodmas_batch_capture(hodmas_batch_t b)
+{
+    if (!valid_batch(b))
+        return HODMAS_EINVAL;
+    if (b->exec)
+        return HODMAS_OK;
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(b->d_buf);
+    const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
+    const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
+    void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void*>(hodmas::batch_kernel(!(b->flags & HODMAS_FLAG_ACC_PLAIN)));
+    kp.gridDim = dim3(b->grid);
+    kp.blockDim = dim3(hodmas::kBlock);
+    kp.sharedMemBytes = (unsigned)b->lds_bytes;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    if (hipGraphCreate(&b->graph, 0) != hipSuccess ||
+        hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) != hipSuccess ||
+        hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+        b->exec = nullptr;
+        return HODMAS_EDEVICE;
+    }
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
+{
+    if (!valid_batch(b) || !b->exec || !b->has_list)
+        return HODMAS_EINVAL;
+    if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return HODMAS_EDEVICE;
+    }
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_batch_get_info(hodmas_batch_t b, hodmas_batch_info* info)
+{
+    if (!valid_batch(b) || !info)
+        return HODMAS_EINVAL;
+    *info = b->info;
+    return HODMAS_OK;
+}
+
+hodmas_status hodmas_batch_destroy(hodmas_batch_t b)
+{
+    if (!b)
+        return HODMAS_OK;
+    if (b->magic != kBatchMagic)
+        return HODMAS_EINVAL;
+    release(b);
+    b->magic = 0;
+    delete b;
+    return HODMAS_OK;
+}
+
+}  // extern "C"

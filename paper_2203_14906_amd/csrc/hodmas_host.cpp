@@ -20,35 +20,15 @@
 
 using hodmas::FrameArgs;
 
+using hodmas::kPlanMagic;
+
 namespace {
 
-constexpr uint32_t kMagic = 0x484f444du;  // "HODM"
+constexpr uint32_t kMagic = kPlanMagic;
 constexpr double kMaxDistanceSamples = 4194304.0;  // 2^22: delays stay exact-integer in float32
 
 }  // namespace
 
-struct hodmas_plan_s {
-    uint32_t magic = kMagic;
-    hodmas_geometry geom{};
-    hodmas_grid grid{};
-    hodmas_rf_desc rf{};
-    int32_t max_order = 0;
-    uint32_t flags = 0;
-    hodmas_tiling tiling{};
-    std::vector<double> elem_x;           // metres
-    double x0s = 0, dxs = 0, z0s = 0, dzs = 0, t0s = 0;
-    std::vector<hodmas_tile_desc> tiles;
-    std::vector<hodmas_chan_entry> entries;
-    std::vector<hodmas_stage_entry> stage;
-    int32_t max_window = 0;
-    int64_t lds_bytes = 0;
-    float in_scale = 1.f, out_scale = 1.f;
-    int device = -1;
-    hodmas_tile_desc* d_tiles = nullptr;
-    hodmas_chan_entry* d_entries = nullptr;
-    hodmas_stage_entry* d_stage = nullptr;
-    int64_t table_bytes = 0;
-};
 
 namespace {
 
@@ -344,20 +324,10 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     return HODMAS_OK;
 }
 
-hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t order,
-                              float* image_dev, void* stream)
+}  // extern "C"
+
+FrameArgs hodmas::frame_args(const hodmas_plan_s* plan, const void* rf_dev, float* image_dev)
 {
-    if (!plan || plan->magic != kMagic || !rf_dev || !image_dev)
-        return HODMAS_EINVAL;
-    if (plan->flags & HODMAS_FLAG_HOST_ONLY)
-        return HODMAS_EINVAL;
-    if (order < 1 || order > plan->max_order || order > HODMAS_MAX_ORDER)
-        return HODMAS_EUNSUPPORTED;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess)
-        return HODMAS_EDEVICE;
-    if (cur != plan->device && hipSetDevice(plan->device) != hipSuccess)
-        return HODMAS_EDEVICE;
     FrameArgs a;
     a.tiles = plan->d_tiles;
     a.entries = plan->d_entries;
@@ -378,6 +348,26 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
     a.dzs = plan->dzs;
     a.in_scale = plan->in_scale;
     a.out_scale = plan->out_scale;
+    return a;
+}
+
+extern "C" {
+
+hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t order,
+                              float* image_dev, void* stream)
+{
+    if (!plan || plan->magic != kMagic || !rf_dev || !image_dev)
+        return HODMAS_EINVAL;
+    if (plan->flags & HODMAS_FLAG_HOST_ONLY)
+        return HODMAS_EINVAL;
+    if (order < 1 || order > plan->max_order || order > HODMAS_MAX_ORDER)
+        return HODMAS_EUNSUPPORTED;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return HODMAS_EDEVICE;
+    if (cur != plan->device && hipSetDevice(plan->device) != hipSuccess)
+        return HODMAS_EDEVICE;
+    const FrameArgs a = hodmas::frame_args(plan, rf_dev, image_dev);
     const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
     int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, plan->lds_bytes, stream);
     if (cur != plan->device)

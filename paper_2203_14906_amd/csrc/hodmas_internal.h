@@ -2,6 +2,8 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
+
 #include "../../include/hodmas.h"
 
 namespace hodmas {
@@ -27,8 +29,65 @@ struct FrameArgs {
     float out_scale;         // frame_max: kernel result -> image units
 };
 
+// Work list of the persistent batched kernel (device memory).
+struct BatchHeader {
+    int32_t n_units;
+    int32_t n_frames;
+    int32_t pad[2];
+};
+
+struct BatchFrame {
+    FrameArgs args;
+    int32_t order;
+    int32_t dtype;
+    int32_t pad[2];
+};
+
+struct BatchUnit {
+    int32_t frame;
+    int32_t tile;
+};
+
 // Launch one frame on `stream`.  Returns hipSuccess or the launch error code.
 int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, int64_t lds_bytes,
                  void* stream);
+
+constexpr uint32_t kPlanMagic = 0x484f444du;  // "HODM"
+
+}  // namespace hodmas
+
+// A plan: validated inputs, float64-derived host tables and their device copies.
+struct hodmas_plan_s {
+    uint32_t magic = hodmas::kPlanMagic;
+    hodmas_geometry geom{};
+    hodmas_grid grid{};
+    hodmas_rf_desc rf{};
+    int32_t max_order = 0;
+    uint32_t flags = 0;
+    hodmas_tiling tiling{};
+    std::vector<double> elem_x;           // metres
+    double x0s = 0, dxs = 0, z0s = 0, dzs = 0, t0s = 0;
+    std::vector<hodmas_tile_desc> tiles;
+    std::vector<hodmas_chan_entry> entries;
+    std::vector<hodmas_stage_entry> stage;
+    int32_t max_window = 0;
+    int64_t lds_bytes = 0;
+    float in_scale = 1.f, out_scale = 1.f;
+    int device = -1;
+    hodmas_tile_desc* d_tiles = nullptr;
+    hodmas_chan_entry* d_entries = nullptr;
+    hodmas_stage_entry* d_stage = nullptr;
+    int64_t table_bytes = 0;
+};
+
+namespace hodmas {
+
+// Kernel arguments of one frame under `plan`.
+FrameArgs frame_args(const hodmas_plan_s* plan, const void* rf_dev, float* image_dev);
+
+// The persistent batched kernel (for graph nodes) and a direct launch of it.
+const void* batch_kernel(bool compensated);
+int launch_batch(const BatchHeader* hdr, const BatchFrame* frames, const BatchUnit* units, int grid,
+                 bool compensated, int64_t lds_bytes, void* stream);
 
 }  // namespace hodmas

@@ -205,11 +205,12 @@ __device__ __forceinline__ R newton(const R (&p)[K])
     return e[K];
 }
 
+// One pixel tile of one frame: stage, accumulate, combine, recover, store.
+// Every thread of the workgroup calls this with the same (A, tile); all
+// branches on tile data are workgroup-uniform, so the barriers inside match.
 template <int K, int DT, bool COMP>
-__global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
+__device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
 {
-    extern __shared__ float lds[];
-    const int tile = blockIdx.x;
     const hodmas_tile_desc td = ConstTile(A.tiles)[tile];
     const int tid = threadIdx.x;
     const int npix = kBlock / A.split;
@@ -221,11 +222,12 @@ __global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
     const bool valid = lx < td.nx && lz < td.nz;
     const int ix = td.ix0 + min(lx, td.nx - 1);
     const int iz = td.iz0 + min(lz, td.nz - 1);
+    float* __restrict__ dst = A.image + (int64_t)iz * A.nx + ix;
 
     if (td.n_active < K) {
         // fewer contributing elements than the order: no K-subset exists, e_K = 0 exactly
         if (g == 0 && valid)
-            A.image[(int64_t)iz * A.nx + ix] = 0.f;
+            *dst = 0.f;
         return;
     }
 
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
     ConstStage St = ConstStage(A.stage) + td.first_entry;
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
-        __syncthreads();
+        __syncthreads();                       // previous readers of the LDS are done
         stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, lane);
         __syncthreads();
         if (td.check)
@@ -290,7 +292,56 @@ __global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
     for (int j = 0; j < K; ++j)
         p[j] = COMP ? R(s[j]) - R(c[j]) : R(s[j]);
     const R ek = newton<K, R>(p);
-    A.image[(int64_t)iz * A.nx + ix] = (float)(ek * R(A.out_scale));
+    *dst = (float)(ek * R(A.out_scale));
+}
+
+template <int K, int DT, bool COMP>
+__global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
+{
+    extern __shared__ float lds[];
+    process_tile<K, DT, COMP>(A, blockIdx.x, lds);
+}
+
+// Persistent form: a fixed grid walks a cost-sorted list of (frame, tile)
+// units of many frames with their own plans, orders and storage types.
+// Workgroup b takes units b, 2G-1-b, 2G+b, ... (a snake over the sorted list,
+// which evens out the per-workgroup cost).  Each tile runs exactly the code the
+// per-frame kernel runs for it, so a frame's image does not depend on the mix.
+template <int DT, bool COMP>
+__device__ __forceinline__ void dispatch_order(const FrameArgs& A, int order, int tile, float* lds)
+{
+    switch (order) {
+    case 1: process_tile<1, DT, COMP>(A, tile, lds); break;
+    case 2: process_tile<2, DT, COMP>(A, tile, lds); break;
+    case 3: process_tile<3, DT, COMP>(A, tile, lds); break;
+    case 4: process_tile<4, DT, COMP>(A, tile, lds); break;
+    case 5: process_tile<5, DT, COMP>(A, tile, lds); break;
+    case 6: process_tile<6, DT, COMP>(A, tile, lds); break;
+    default: break;
+    }
+}
+
+template <bool COMP>
+__global__ __launch_bounds__(kBlock) void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr,
+                                                              const BatchFrame* __restrict__ frames,
+                                                              const BatchUnit* __restrict__ units)
+{
+    extern __shared__ float lds[];
+    const int n = hdr->n_units;
+    const int G = gridDim.x;
+    for (int r = 0; r * G < n; ++r) {
+        const int u = (r & 1) ? (r + 1) * G - 1 - (int)blockIdx.x : r * G + (int)blockIdx.x;
+        if (u >= n)
+            continue;
+        const BatchUnit un = units[u];
+        const BatchFrame& fr = frames[un.frame];
+        switch (fr.dtype) {
+        case HODMAS_F32: dispatch_order<HODMAS_F32, COMP>(fr.args, fr.order, un.tile, lds); break;
+        case HODMAS_F16: dispatch_order<HODMAS_F16, COMP>(fr.args, fr.order, un.tile, lds); break;
+        case HODMAS_I16: dispatch_order<HODMAS_I16, COMP>(fr.args, fr.order, un.tile, lds); break;
+        default: break;
+        }
+    }
 }
 
 template <int K, int DT>
@@ -330,6 +381,25 @@ int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, int
     case HODMAS_I16: return launch_dt<HODMAS_I16>(a, order, compensated, lds_bytes, st);
     }
     return (int)hipErrorInvalidValue;
+}
+
+const void* batch_kernel(bool compensated)
+{
+    return compensated ? reinterpret_cast<const void*>(&hodmas_batch_kernel<true>)
+                       : reinterpret_cast<const void*>(&hodmas_batch_kernel<false>);
+}
+
+int launch_batch(const BatchHeader* hdr, const BatchFrame* frames, const BatchUnit* units, int grid,
+                 bool compensated, int64_t lds_bytes, void* stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (compensated)
+        hipLaunchKernelGGL((hodmas_batch_kernel<true>), dim3(grid), dim3(kBlock), (size_t)lds_bytes, st,
+                           hdr, frames, units);
+    else
+        hipLaunchKernelGGL((hodmas_batch_kernel<false>), dim3(grid), dim3(kBlock), (size_t)lds_bytes, st,
+                           hdr, frames, units);
+    return (int)hipGetLastError();
 }
 
 }  // namespace hodmas

@@ -74,6 +74,11 @@ class ChanEntry(ctypes.Structure):
                 ("off", ctypes.c_int32), ("channel", ctypes.c_int32)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("n_units", ctypes.c_int64), ("grid", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int64), ("pixel_channels", ctypes.c_int64)]
+
+
 class StageEntry(ctypes.Structure):
     _fields_ = [("channel", ctypes.c_int32), ("first_sample", ctypes.c_int32)]
 
@@ -100,6 +105,21 @@ def _load():
                                      ctypes.POINTER(ctypes.POINTER(ChanEntry)),
                                      ctypes.POINTER(ctypes.POINTER(StageEntry)),
                                      ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
+    L.hodmas_batch_create.restype = i32
+    L.hodmas_batch_create.argtypes = [i32, ctypes.c_int64, ctypes.c_int64, u32, ctypes.POINTER(vp)]
+    L.hodmas_batch_set.restype = i32
+    L.hodmas_batch_set.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                   ctypes.POINTER(vp), i32, vp]
+    L.hodmas_batch_launch.restype = i32
+    L.hodmas_batch_launch.argtypes = [vp, vp]
+    L.hodmas_batch_capture.restype = i32
+    L.hodmas_batch_capture.argtypes = [vp]
+    L.hodmas_batch_replay.restype = i32
+    L.hodmas_batch_replay.argtypes = [vp, vp]
+    L.hodmas_batch_get_info.restype = i32
+    L.hodmas_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.hodmas_batch_destroy.restype = i32
+    L.hodmas_batch_destroy.argtypes = [vp]
     L.hodmas_version.restype = ctypes.c_char_p
     L.hodmas_version.argtypes = []
     return L
@@ -199,6 +219,59 @@ class Plan:
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.hodmas_destroy(self._h)
         self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many frames (own plan, order, storage each) in one persistent launch."""
+
+    def __init__(self, max_frames, max_units, max_lds_bytes=0, flags=0):
+        h = ctypes.c_void_p()
+        _check(lib.hodmas_batch_create(int(max_frames), int(max_units), int(max_lds_bytes), int(flags),
+                                       ctypes.byref(h)), "hodmas_batch_create")
+        self._h = h
+        self._keep = None
+
+    def set(self, plans, rfs, orders, images, stream=None):
+        n = len(plans)
+        if not (len(rfs) == len(orders) == len(images) == n):
+            raise ValueError("plans, rfs, orders and images must have the same length")
+        for p, r, o in zip(plans, rfs, images):
+            _check_tensor(r, p)
+            if o.dtype.__str__() != "torch.float32" or not o.is_contiguous() or o.numel() != p.nx * p.nz:
+                raise ValueError("each image must be a contiguous float32 tensor of nz*nx elements")
+        ph = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+        pr = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rfs])
+        po = (ctypes.c_int32 * n)(*[int(k) for k in orders])
+        pi = (ctypes.c_void_p * n)(*[o.data_ptr() for o in images])
+        _check(lib.hodmas_batch_set(self._h, ph, pr, po, pi, n, _stream_handle(stream)),
+               "hodmas_batch_set")
+        self._keep = (list(plans), list(rfs), list(images))   # keep the memory alive
+
+    def launch(self, stream=None):
+        _check(lib.hodmas_batch_launch(self._h, _stream_handle(stream)), "hodmas_batch_launch")
+
+    def capture(self):
+        _check(lib.hodmas_batch_capture(self._h), "hodmas_batch_capture")
+
+    def replay(self, stream=None):
+        _check(lib.hodmas_batch_replay(self._h, _stream_handle(stream)), "hodmas_batch_replay")
+
+    def info(self) -> BatchInfo:
+        inf = BatchInfo()
+        _check(lib.hodmas_batch_get_info(self._h, ctypes.byref(inf)), "hodmas_batch_get_info")
+        return inf
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.hodmas_batch_destroy(self._h)
+        self._h = ctypes.c_void_p()
+        self._keep = None
 
     def __del__(self):
         try:

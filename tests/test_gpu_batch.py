@@ -1,0 +1,148 @@
+"""Batched form on the GPU: a mixed batch in one persistent launch gives every
+frame bitwise the image of its own per-frame launch (so parity carries over),
+graph replays match the eager launch, and bad work lists are refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2203_14906_amd import phantom as ph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2203_14906_amd import hodmas
+    return hodmas
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SPECS = [  # (N, S, nx, nz, order, dtype)
+    (64, 1024, 96, 80, 1, "f32"), (128, 2048, 128, 128, 6, "f16"), (32, 512, 37, 53, 3, "i16"),
+    (64, 1024, 64, 64, 4, "f16"), (16, 600, 40, 24, 2, "f32"), (128, 1024, 200, 100, 5, "i16"),
+    (256, 2048, 64, 96, 2, "f16"), (8, 300, 17, 19, 6, "f32"), (64, 2048, 150, 150, 3, "f32"),
+    (4, 256, 12, 12, 6, "f16"),  # order above the element count: zero image
+]
+
+
+def make_batch_inputs(hd, specs, seed0=500):
+    plans, rfs, outs, orders, frames = [], [], [], [], []
+    for i, (n, S, nx, nz, k, dt) in enumerate(specs):
+        f = ph.make_frame(n, S, nx, nz, n_points=5, n_lines=1, snr_db=15.0, seed=seed0 + i)
+        if dt == "f32":
+            arr, scale = ph.to_fp32(f.rf), 1.0
+        elif dt == "f16":
+            arr, scale = ph.to_fp16(f.rf), 1.0
+        else:
+            arr, scale = ph.to_int16(f.rf, seed0 + i)
+        plans.append(hd.Plan(f.geometry, f.grid, S, dt, max_order=6, dequant_scale=float(scale)))
+        rfs.append(torch.from_numpy(arr).cuda())
+        outs.append(torch.full((nz, nx), float("nan"), dtype=torch.float32, device="cuda"))
+        orders.append(k)
+        frames.append((f, arr, float(scale)))
+    return plans, rfs, outs, orders, frames
+
+
+def test_mixed_batch_equals_per_frame_launches(hd):
+    plans, rfs, outs, orders, frames = make_batch_inputs(hd, SPECS)
+    alone = [p.beamform(r, k) for p, r, k in zip(plans, rfs, orders)]
+    torch.cuda.synchronize()
+    batch = hd.Batch(max_frames=32, max_units=100000)
+    batch.set(plans, rfs, orders, outs)
+    inf = batch.info()
+    say("batch: %d frames, %d units, grid %d, lds %d" % (inf.n_frames, inf.n_units, inf.grid, inf.lds_bytes))
+    batch.launch()
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(alone, outs)):
+        assert torch.equal(a, b), "frame %d differs between the batch and its own launch" % i
+    # spot parity of two members against the oracle
+    for i in (1, 5):
+        f, arr, scale = frames[i]
+        o = O.beamform(arr, f.geometry, f.grid, orders[i], dequant_scale=scale if arr.dtype == np.int16 else None)
+        g = outs[i].cpu().numpy().astype(np.float64)
+        err = np.linalg.norm(g - o) / np.linalg.norm(o)
+        say("batch member %d (order %d, %s) rel L2 %.3e" % (i, orders[i], arr.dtype, err))
+        assert err <= 2e-5
+    assert torch.all(outs[-1] == 0)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_graph_replays_and_reset_work_list(hd):
+    plans, rfs, outs, orders, _ = make_batch_inputs(hd, SPECS[:6], seed0=700)
+    alone = [p.beamform(r, k).clone() for p, r, k in zip(plans, rfs, orders)]
+    batch = hd.Batch(max_frames=16, max_units=50000)
+    batch.set(plans, rfs, orders, outs)
+    batch.capture()
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        batch.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i, (a, b) in enumerate(zip(alone, outs)):
+            assert torch.equal(a, b), "replay %d frame %d" % (rep, i)
+    # a new work list (other orders, reversed frames) is read by the same graph
+    orders2 = [(k % 6) + 1 for k in orders][::-1]
+    plans2, rfs2, outs2 = plans[::-1], rfs[::-1], outs[::-1]
+    batch.set(plans2, rfs2, orders2, outs2)
+    batch.replay()
+    torch.cuda.synchronize()
+    for p, r, k, o in zip(plans2, rfs2, orders2, outs2):
+        assert torch.equal(p.beamform(r, k), o)
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_batch_rejects_bad_work_lists(hd):
+    f = ph.make_frame(16, 256, 20, 20, n_points=2, seed=3)
+    p4 = hd.Plan(f.geometry, f.grid, 256, "f32", max_order=4)
+    plain = hd.Plan(f.geometry, f.grid, 256, "f32", max_order=6, flags=hd.FLAG_ACC_PLAIN)
+    host = hd.Plan(f.geometry, f.grid, 256, "f32", max_order=6, flags=hd.FLAG_HOST_ONLY)
+    rf = torch.from_numpy(ph.to_fp32(f.rf)).cuda()
+    out = torch.empty((20, 20), dtype=torch.float32, device="cuda")
+    b = hd.Batch(max_frames=2, max_units=10000)
+    with pytest.raises(hd.HodmasError) as e:
+        b.set([p4], [rf], [5], [out])
+    assert e.value.status == hd.EUNSUPPORTED
+    with pytest.raises(hd.HodmasError) as e:
+        b.set([plain], [rf], [2], [out])
+    assert e.value.status == hd.EINVAL
+    with pytest.raises(hd.HodmasError) as e:
+        b.set([host], [rf], [2], [out])
+    assert e.value.status == hd.EINVAL
+    with pytest.raises(hd.HodmasError) as e:
+        b.set([p4, p4, p4], [rf] * 3, [1] * 3, [out] * 3)
+    assert e.value.status == hd.EINVAL
+    small = hd.Batch(max_frames=2, max_units=1)
+    with pytest.raises(hd.HodmasError) as e:
+        small.set([p4], [rf], [1], [out])
+    assert e.value.status == hd.EINVAL
+    tiny_lds = hd.Batch(max_frames=2, max_units=10000, max_lds_bytes=256)
+    with pytest.raises(hd.HodmasError) as e:
+        tiny_lds.set([p4], [rf], [1], [out])
+    assert e.value.status == hd.EINVAL
+    with pytest.raises(hd.HodmasError) as e:
+        b.launch()                      # nothing set yet
+    assert e.value.status == hd.EINVAL
+    pl = hd.Batch(max_frames=2, max_units=10000, flags=hd.FLAG_ACC_PLAIN)
+    pl.set([plain], [rf], [3], [out])
+    pl.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(out, plain.beamform(rf, 3))
+    for x in (b, small, tiny_lds, pl):
+        x.close()
+    for x in (p4, plain, host):
+        x.close()

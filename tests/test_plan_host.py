@@ -162,3 +162,19 @@ def test_default_tiling_and_info():
     assert small.info().tiling.split in (2, 4)
     p.close()
     small.close()
+
+
+def test_batch_argument_validation_without_device():
+    L = hodmas.lib
+    h = ctypes.c_void_p()
+    assert L.hodmas_batch_create(0, 10, 0, 0, ctypes.byref(h)) == hodmas.EINVAL
+    assert L.hodmas_batch_create(4, 0, 0, 0, ctypes.byref(h)) == hodmas.EINVAL
+    assert L.hodmas_batch_create(4, 10, -1, 0, ctypes.byref(h)) == hodmas.EINVAL
+    assert L.hodmas_batch_create(4, 10, 1 << 30, 0, ctypes.byref(h)) == hodmas.EINVAL
+    assert L.hodmas_batch_create(4, 10, 0, 0x80, ctypes.byref(h)) == hodmas.EINVAL
+    assert L.hodmas_batch_create(4, 10, 0, 0, None) == hodmas.EINVAL
+    assert L.hodmas_batch_destroy(None) == hodmas.OK
+    assert L.hodmas_batch_launch(None, None) == hodmas.EINVAL
+    assert L.hodmas_batch_replay(None, None) == hodmas.EINVAL
+    assert L.hodmas_batch_capture(None) == hodmas.EINVAL
+    assert L.hodmas_batch_set(None, None, None, None, None, 1, None) == hodmas.EINVAL
