@@ -36,6 +36,13 @@ VALU_PEAK_TSLOT = 78.64
 
 def parse():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="plain", choices=["plain", "reduced", "batch", "serve"],
+                    help="plain: 128 el / 512^2 / FP32 (default); reduced: 256 el / 1024^2 / int16+FP16; "
+                         "batch: 256 mixed FP16 frames in one persistent launch vs 256 FP32 launches; "
+                         "serve: Poisson arrivals, continuous batching vs plain FP32 per request")
+    ap.add_argument("--rates", default="500,1000,2000", help="serve: arrival rates (frames/s)")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds per rate")
+    ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM admission budget")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -54,9 +61,17 @@ def main():
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2203_14906_amd import hodmas, phantom as ph
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    {"plain": bench_plain, "reduced": bench_reduced, "batch": bench_batch,
+     "serve": bench_serve}[args.workload](args, torch)
+
+
+def _events(torch, n):
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+
+
+def bench_plain(args, torch):
+    from paper_2203_14906_amd import hodmas, phantom as ph
     dev = torch.device("cuda:0")
     orders = [int(k) for k in args.orders.split(",")]
     p = ph.CONFIGS[2]
@@ -158,6 +173,177 @@ def main():
     }
     print(json.dumps(res))
     plan.close()
+
+
+def bench_reduced(args, torch):
+    """256 elements, 1024^2, int16 and FP16 storage, k = 1..6: throughput per
+    order and relative L2 per order against the FP64 oracle on the same stored
+    values (gated in the tests) and on the float64 RF before quantisation."""
+    import numpy as np
+    from oracle import oracle
+    from paper_2203_14906_amd import hodmas, phantom as ph
+    f = ph.config_frame(3)
+    geom, grid = f.geometry, f.grid
+    pixch = grid.nx * grid.nz * f.rf.shape[0]
+    rng = np.random.default_rng(1)
+    ix = rng.integers(0, grid.nx, 4096).astype(np.int32)
+    iz = rng.integers(0, grid.nz, 4096).astype(np.int32)
+    res = {"metric": "beamformed Gpixel*ch/s per order, reduced-precision storage", "unit": "Gpixel*ch/s",
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "256 elements, 2048 samples/channel, 1024x1024 grid, int16 and FP16 RF"},
+           "forms": {}}
+    for dt in ("i16", "f16"):
+        if dt == "i16":
+            arr, scale = ph.to_int16(f.rf, 3000)
+            scale = float(scale)
+        else:
+            arr, scale = ph.to_fp16(f.rf), 1.0
+        plan = hodmas.Plan(geom, grid, arr.shape[1], dt, max_order=6, dequant_scale=scale)
+        rf_dev = torch.from_numpy(arr).cuda()
+        out = torch.empty((grid.nz, grid.nx), dtype=torch.float32, device="cuda")
+        form = {}
+        for k in range(1, 7):
+            for _ in range(args.warmup):
+                plan.beamform(rf_dev, k, out)
+            ev = _events(torch, 1)[0]
+            ev[0].record()
+            for _ in range(args.steps):
+                plan.beamform(rf_dev, k, out)
+            ev[1].record()
+            torch.cuda.synchronize()
+            us = ev[0].elapsed_time(ev[1]) / args.steps * 1e3
+            g = out.cpu().numpy().astype(np.float64)[iz, ix]
+            same = oracle.beamform(arr, geom, grid, k, dequant_scale=scale if dt == "i16" else None,
+                                   pixels=(ix, iz))
+            pre = oracle.beamform(f.rf, geom, grid, k, pixels=(ix, iz))
+            form[str(k)] = {"kernel_us": round(us, 2), "gpixch_s": round(pixch / (us * 1e-6) / 1e9, 2),
+                            "rel_l2_same_values": float("%.3e" % (np.linalg.norm(g - same) / np.linalg.norm(same))),
+                            "rel_l2_vs_fp64_rf": float("%.3e" % (np.linalg.norm(g - pre) / np.linalg.norm(pre)))}
+        res["forms"][dt] = form
+        plan.close()
+    res["sample"] = "relative L2 over 4096 seeded pixels"
+    print(json.dumps(res))
+
+
+def _mixed_frames(torch, specs, with_fp32):
+    """Device-resident frames of the mixed workload; the RF of each (N, S)
+    shape comes from one seeded phantom shared by the frames of that shape."""
+    from paper_2203_14906_amd import hodmas, phantom as ph
+    rf_cache, plans, frames = {}, {}, []
+    for sp in specs:
+        n, S, side = sp["n_elements"], sp["n_samples"], sp["side"]
+        if (n, S) not in rf_cache:
+            fr = ph.make_frame(n, S, 8, 8, n_points=50, n_lines=3, snr_db=10.0, seed=4000 + n + S)
+            rf_cache[(n, S)] = (torch.from_numpy(ph.to_fp16(fr.rf)).cuda(),
+                                torch.from_numpy(ph.to_fp32(fr.rf)).cuda() if with_fp32 else None)
+        if (n, S, side) not in plans:
+            w, d = ph.field_of_view(n, S)
+            grid = ph.make_grid(side, side, w, d)
+            geom = ph.Geometry(n)
+            plans[(n, S, side)] = (hodmas.Plan(geom, grid, S, "f16", max_order=6),
+                                   hodmas.Plan(geom, grid, S, "f32", max_order=6) if with_fp32 else None)
+        frames.append(dict(spec=sp, rf16=rf_cache[(n, S)][0], rf32=rf_cache[(n, S)][1],
+                           plan16=plans[(n, S, side)][0], plan32=plans[(n, S, side)][1],
+                           pixch=side * side * n))
+    return frames, plans
+
+
+def bench_batch(args, torch):
+    """256 mixed frames (N, S, grid side, order drawn per frame; FP16 RF) in one
+    persistent launch replayed from a HIP graph, against 256 plain per-frame
+    FP32 launches on one stream.  All frames are submitted at t = 0; latency is
+    each frame's completion time."""
+    import numpy as np
+    from paper_2203_14906_amd import hodmas, phantom as ph
+    specs = ph.mixed_batch_specs(256, seed=4000)
+    frames, plans = _mixed_frames(torch, specs, with_fp32=True)
+    outs_b = [torch.empty((f["spec"]["side"],) * 2, dtype=torch.float32, device="cuda") for f in frames]
+    outs_p = [torch.empty_like(o) for o in outs_b]
+    orders = [f["spec"]["order"] for f in frames]
+    lds = max(p[0].info().lds_bytes for p in plans.values())
+    batch = hodmas.Batch(max_frames=256, max_units=1 << 22, max_lds_bytes=lds)
+    batch.set([f["plan16"] for f in frames], [f["rf16"] for f in frames], orders, outs_b)
+    batch.capture()
+    for _ in range(args.warmup):
+        batch.replay()
+        for f, o, k in zip(frames, outs_p, orders):
+            f["plan32"].beamform(f["rf32"], k, o)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 4)
+    tb = []
+    for _ in range(reps):
+        ev = _events(torch, 1)[0]
+        ev[0].record()
+        batch.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        tb.append(ev[0].elapsed_time(ev[1]))
+    tp, lat_p = [], []
+    for _ in range(reps):
+        start = torch.cuda.Event(enable_timing=True)
+        ends = [torch.cuda.Event(enable_timing=True) for _ in frames]
+        start.record()
+        for f, o, k, e in zip(frames, outs_p, orders, ends):
+            f["plan32"].beamform(f["rf32"], k, o)
+            e.record()
+        torch.cuda.synchronize()
+        tp.append(start.elapsed_time(ends[-1]))
+        lat_p.append([start.elapsed_time(e) for e in ends])
+    tb_ms, tp_ms = float(np.median(tb)), float(np.median(tp))
+    lat_p = np.array(lat_p[int(np.argsort(tp)[len(tp) // 2])])
+    pixch = sum(f["pixch"] for f in frames)
+    worst = 0.0
+    for f, ob, op in zip(frames[:16], outs_b[:16], outs_p[:16]):
+        a, b = ob.double(), op.double()
+        worst = max(worst, float(torch.linalg.norm(a - b) / torch.linalg.norm(b).clamp_min(1e-300)))
+    inf = batch.info()
+    res = {"metric": "frames/s and p99 latency, batched (one persistent launch) vs plain per-frame FP32",
+           "unit": "frames/s", "n_gpus": 1, "data": "synthetic", "dtype": "f16 storage / f32 compute",
+           "config": {"workload": "256 mixed frames: N in {64,128,256}, S in {1024,2048,4096}, "
+                                  "grid side in {256,512,768,1024}, order 1..6, seed 4000",
+                      "units": inf.n_units, "grid": inf.grid, "lds_bytes": inf.lds_bytes},
+           "batched": {"frames_per_s": round(256 / (tb_ms * 1e-3), 1), "batch_ms": round(tb_ms, 3),
+                       "p50_ms": round(tb_ms, 3), "p99_ms": round(tb_ms, 3),
+                       "gpixch_s": round(pixch / (tb_ms * 1e-3) / 1e9, 1)},
+           "plain_fp32": {"frames_per_s": round(256 / (tp_ms * 1e-3), 1), "total_ms": round(tp_ms, 3),
+                          "p50_ms": round(float(np.percentile(lat_p, 50)), 3),
+                          "p99_ms": round(float(np.percentile(lat_p, 99)), 3),
+                          "gpixch_s": round(pixch / (tp_ms * 1e-3) / 1e9, 1)},
+           "speedup": round(tp_ms / tb_ms, 3),
+           "rel_l2_batched_fp16_vs_plain_fp32_first16": float("%.3e" % worst),
+           "pixel_channels": pixch}
+    print(json.dumps(res))
+    batch.close()
+    for p16, p32 in plans.values():
+        p16.close()
+        p32.close()
+
+
+def bench_serve(args, torch):
+    """Poisson arrivals at each rate for --duration s; continuous batching of
+    FP16 frames vs a plain synchronous FP32 launch per request."""
+    from paper_2203_14906_amd import serve
+    pool = serve.FramePool(torch, "cuda", seed=5000)
+    out = {"metric": "p50/p99 latency and sustained frames/s, continuous batching vs plain FP32",
+           "unit": "frames/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "Poisson arrivals, mixed N/S/grid/order frames from a pool of %d "
+                                  "resident frames (%d resident plans)" % (len(pool.frames), len(pool._plans)),
+                      "duration_s": args.duration, "budget_gb": args.budget_gb},
+           "rates": {}}
+    warm = serve.poisson_requests(500.0, 0.5, len(pool.frames), seed=1)
+    srv = serve.Server(torch, pool, slots=3, budget_bytes=int(args.budget_gb * (1 << 30)))
+    srv.run(warm)
+    serve.run_plain(torch, pool, warm[:50])
+    for rate in [float(r) for r in args.rates.split(",")]:
+        reqs = serve.poisson_requests(rate, args.duration, len(pool.frames), seed=int(rate))
+        b = srv.run(reqs).summary()
+        reqs = serve.poisson_requests(rate, args.duration, len(pool.frames), seed=int(rate))
+        p = serve.run_plain(torch, pool, reqs).summary()
+        out["rates"][str(int(rate))] = {"batched": b, "plain_fp32": p}
+        print("rate %g: batched %s | plain %s" % (rate, b, p), file=sys.stderr, flush=True)
+    srv.close()
+    pool.close()
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

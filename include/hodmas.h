@@ -143,6 +143,17 @@ hodmas_status hodmas_destroy(hodmas_plan_t plan);
 /* Static description of a status code (never NULL). */
 const char* hodmas_status_string(hodmas_status status);
 
+/* Choose a tiling for this geometry, grid, RF layout and order by timing the
+ * candidate tilings (tile shape, element split, LDS chunk) on the current
+ * device on a zero record (timing does not depend on sample values).  With a
+ * cache_path, results are appended to / looked up in that JSON-lines file,
+ * keyed by device architecture and every input that changes the plan.
+ * Allocates and frees scratch device memory; not for the hot path.
+ * Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED (no candidate could run). */
+hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const hodmas_grid* grid,
+                              const hodmas_rf_desc* rf, int32_t order, uint32_t flags,
+                              const char* cache_path, hodmas_tiling* out);
+
 /* Plan summary, for callers that size work or report throughput. */
 typedef struct {
     int32_t n_elements, n_samples, nx, nz;
@@ -176,7 +187,7 @@ typedef struct {
     float d0;                    /* anchor-to-element distance */
     float frac0;                 /* fractional part of the anchor delay */
     float lo, hi;                /* valid delays relative to floor(anchor delay) */
-    int32_t off;                 /* LDS index of floor(anchor delay) */
+    int32_t off;                 /* LDS byte offset of floor(anchor delay) */
     int32_t channel;             /* element index */
 } hodmas_chan_entry;
 
@@ -192,11 +203,14 @@ hodmas_status hodmas_plan_tables(hodmas_plan_t plan, const hodmas_tile_desc** ti
 
 /* ---------------------------------------------------------------------------
  * Batched form: many frames -- each with its own plan, order and storage type --
- * in one persistent launch.  The library builds a work list of (frame, tile)
- * units sorted by estimated cost and a fixed grid of workgroups walks it.  Each
- * tile runs exactly the per-frame code, so every frame's image is bitwise the
- * same as from hodmas_beamform with its plan, whatever else is in the batch.
- * A batch object is used from one stream at a time.
+ * in one submission.  The library builds a work list of (frame, tile) units,
+ * grouped by kind (order x storage type) and sorted by estimated cost within a
+ * kind; one persistent kernel per kind present walks its slice with a fixed
+ * grid.  A captured graph chains the kernels of all kinds, so one graph launch
+ * runs the whole batch.  Each tile runs exactly the per-frame code, so every
+ * frame's image is bitwise the same as from hodmas_beamform with its plan,
+ * whatever else is in the batch.  A batch object is used from one stream at a
+ * time.
  * ------------------------------------------------------------------------- */
 typedef struct hodmas_batch_s* hodmas_batch_t;
 
@@ -219,11 +233,12 @@ hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
                                const void* const* rf, const int32_t* orders,
                                float* const* images, int32_t n_frames, void* stream);
 
-/* One persistent launch over the current work list on `stream`. */
+/* Run the current work list on `stream`: one persistent launch per kind present. */
 hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
 
-/* Build (once) a HIP graph holding the persistent launch; it reads the work
- * list from device memory, so later hodmas_batch_set calls need no re-capture.
+/* Build (once) a HIP graph chaining the persistent kernels of every kind; they
+ * read the work list from device memory (a kind absent from it returns at
+ * once), so later hodmas_batch_set calls need no re-capture.
  * hodmas_batch_replay launches that graph on `stream`. */
 hodmas_status hodmas_batch_capture(hodmas_batch_t batch);
 hodmas_status hodmas_batch_replay(hodmas_batch_t batch, void* stream);
@@ -232,7 +247,7 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t batch, void* stream);
 typedef struct {
     int32_t n_frames;
     int64_t n_units;
-    int32_t grid;                /* persistent workgroups */
+    int32_t grid;                /* persistent workgroups (largest over kinds) */
     int64_t lds_bytes;           /* dynamic LDS per workgroup */
     int64_t pixel_channels;      /* sum over frames of nx*nz*N */
 } hodmas_batch_info;

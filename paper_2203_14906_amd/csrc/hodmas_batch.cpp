@@ -1,5 +1,6 @@
-// Batched form: a work list of (frame, tile) units over many frames, walked by
-// one persistent launch (optionally replayed from a HIP graph).
+// Batched form: a work list of (frame, tile) units over many frames, grouped by
+// kind (order x storage type) and walked by one persistent kernel per kind;
+// a HIP graph chains the kernels so one graph launch runs the batch.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -33,13 +34,14 @@ struct hodmas_batch_s {
     int64_t max_units = 0;
     int64_t lds_bytes = 0;
     uint32_t flags = 0;
-    int grid = 0;
+    int grid[hodmas::kBatchKinds] = {};   // persistent workgroups per kind
     size_t off_frames = 0, off_units = 0, bytes = 0;
     char* d_buf = nullptr;
     char* h_buf = nullptr;           // pinned staging of the work list
     hipEvent_t copied = nullptr;     // last host->device copy of h_buf
     bool copy_pending = false;
     bool has_list = false;
+    int32_t begin[hodmas::kBatchKinds] = {}, end[hodmas::kBatchKinds] = {};   // host copy of the ranges
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hodmas_batch_info info{};
@@ -92,21 +94,28 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
         delete b;
         return HODMAS_EDEVICE;
     }
-    const void* fn = hodmas::batch_kernel(comp);
-    if (b->lds_bytes > 64 * 1024 &&
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        delete b;
-        return HODMAS_EUNSUPPORTED;
+    int max_grid = 0;
+    for (int k = 1; k <= HODMAS_MAX_ORDER; ++k) {
+        for (int dt = 0; dt < 3; ++dt) {
+            const void* fn = hodmas::batch_kernel(k, dt, comp);
+            if (b->lds_bytes > 64 * 1024 &&
+                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) !=
+                    hipSuccess) {
+                (void)hipGetLastError();
+                delete b;
+                return HODMAS_EUNSUPPORTED;
+            }
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)b->lds_bytes) !=
+                    hipSuccess || per_cu < 1) {
+                (void)hipGetLastError();
+                delete b;
+                return HODMAS_EUNSUPPORTED;
+            }
+            b->grid[hodmas::batch_kind(k, dt)] = per_cu * prop.multiProcessorCount;
+            max_grid = std::max(max_grid, per_cu * prop.multiProcessorCount);
+        }
     }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)b->lds_bytes) !=
-            hipSuccess || per_cu < 1) {
-        (void)hipGetLastError();
-        delete b;
-        return HODMAS_EUNSUPPORTED;
-    }
-    b->grid = per_cu * prop.multiProcessorCount;
     b->off_frames = align_up(sizeof(BatchHeader));
     b->off_units = b->off_frames + align_up(sizeof(BatchFrame) * (size_t)max_frames);
     b->bytes = b->off_units + align_up(sizeof(BatchUnit) * (size_t)max_units);
@@ -124,7 +133,7 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
         delete b;
         return HODMAS_EDEVICE;
     }
-    b->info.grid = b->grid;
+    b->info.grid = max_grid;
     b->info.lds_bytes = b->lds_bytes;
     *out = b;
     return HODMAS_OK;
@@ -139,7 +148,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
         return HODMAS_EINVAL;
     struct Unit {
         int64_t cost;
-        int32_t frame, tile;
+        int32_t kind, frame, tile;
     };
     std::vector<Unit> units;
     int64_t pixch = 0;
@@ -165,14 +174,16 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
                 int64_t cost = pix;  // zero-fill only
                 if (td.n_active >= orders[f])
                     cost = td.n_active * (pix * kSlots[orders[f]] + int64_t(td.window) * 2);
-                units.push_back(Unit{cost, f, (int32_t)t});
+                units.push_back(Unit{cost, hodmas::batch_kind(orders[f], p->rf.dtype), f, (int32_t)t});
             }
         }
     } catch (const std::bad_alloc&) {
         return HODMAS_ENOMEM;
     }
-    std::stable_sort(units.begin(), units.end(),
-                     [](const Unit& x, const Unit& y) { return x.cost > y.cost; });
+    // grouped by kind (one persistent kernel each), heaviest units first within a kind
+    std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) {
+        return x.kind != y.kind ? x.kind < y.kind : x.cost > y.cost;
+    });
     // the pinned staging buffer may still feed the previous asynchronous copy
     if (b->copy_pending && hipEventSynchronize(b->copied) != hipSuccess)
         return HODMAS_EDEVICE;
@@ -183,6 +194,16 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
     std::memset(hdr, 0, sizeof(BatchHeader));
     hdr->n_units = (int32_t)units.size();
     hdr->n_frames = n_frames;
+    for (int k = 0; k < hodmas::kBatchKinds; ++k)
+        hdr->begin[k] = hdr->end[k] = 0;
+    for (size_t u = 0; u < units.size(); ++u) {
+        const int k = units[u].kind;
+        if (u == 0 || units[u - 1].kind != k)
+            hdr->begin[k] = (int32_t)u;
+        hdr->end[k] = (int32_t)u + 1;
+    }
+    std::memcpy(b->begin, hdr->begin, sizeof(b->begin));
+    std::memcpy(b->end, hdr->end, sizeof(b->end));
     for (int32_t f = 0; f < n_frames; ++f) {
         std::memset(&frames[f], 0, sizeof(BatchFrame));
         frames[f].args = hodmas::frame_args(plans[f], rf[f], images[f]);
@@ -213,11 +234,25 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(b->d_buf);
     const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
-    int rc = hodmas::launch_batch(hdr, frames, units, b->grid, !(b->flags & HODMAS_FLAG_ACC_PLAIN),
-                                  b->lds_bytes, stream);
-    return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
+    const bool comp = !(b->flags & HODMAS_FLAG_ACC_PLAIN);
+    for (int k = 1; k <= HODMAS_MAX_ORDER; ++k) {
+        for (int dt = 0; dt < 3; ++dt) {
+            const int kind = hodmas::batch_kind(k, dt);
+            if (b->end[kind] <= b->begin[kind])
+                continue;
+            const int grid = (int)std::min<int64_t>(b->grid[kind], b->end[kind] - b->begin[kind]);
+            if (hodmas::launch_batch(k, dt, hdr, frames, units, grid, comp, b->lds_bytes, stream) != 0) {
+                (void)hipGetLastError();
+                return HODMAS_EDEVICE;
+            }
+        }
+    }
+    return HODMAS_OK;
 }
 
+// The graph chains one node per kind; each reads its unit range from the
+// device header, so a node whose kind is absent from the current work list
+// returns at once and later hodmas_batch_set calls need no re-capture.
 hodmas_status hodmas_batch_capture(hodmas_batch_t b)
 {
     if (!valid_batch(b))
@@ -228,18 +263,28 @@ hodmas_status hodmas_batch_capture(hodmas_batch_t b)
     const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
-    hipKernelNodeParams kp;
-    std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void*>(hodmas::batch_kernel(!(b->flags & HODMAS_FLAG_ACC_PLAIN)));
-    kp.gridDim = dim3(b->grid);
-    kp.blockDim = dim3(hodmas::kBlock);
-    kp.sharedMemBytes = (unsigned)b->lds_bytes;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-    hipGraphNode_t node;
-    if (hipGraphCreate(&b->graph, 0) != hipSuccess ||
-        hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) != hipSuccess ||
-        hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    const bool comp = !(b->flags & HODMAS_FLAG_ACC_PLAIN);
+    bool ok = hipGraphCreate(&b->graph, 0) == hipSuccess;
+    hipGraphNode_t prev = nullptr;
+    for (int k = 1; k <= HODMAS_MAX_ORDER && ok; ++k) {
+        for (int dt = 0; dt < 3 && ok; ++dt) {
+            hipKernelNodeParams kp;
+            std::memset(&kp, 0, sizeof(kp));
+            kp.func = const_cast<void*>(hodmas::batch_kernel(k, dt, comp));
+            kp.gridDim = dim3(b->grid[hodmas::batch_kind(k, dt)]);
+            kp.blockDim = dim3(hodmas::kBlock);
+            kp.sharedMemBytes = (unsigned)b->lds_bytes;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node = nullptr;
+            ok = hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp) ==
+                 hipSuccess;
+            prev = node;
+        }
+    }
+    if (ok)
+        ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;

@@ -148,6 +148,7 @@ hodmas_status build_tables(hodmas_plan_s* p)
         return HODMAS_ENOMEM;
     }
     const int chunk = p->tiling.chunk;
+    const int split = p->tiling.split;
     int32_t max_window = 2;
     std::vector<int32_t> T0(n), wlo(n), whi(n);
     std::vector<float> fr(n), aa(n), d0sq(n), d0(n);
@@ -197,22 +198,34 @@ hodmas_status build_tables(hodmas_plan_s* p)
             td.check = check ? 1 : 0;
             td.first_entry = (int32_t)p->entries.size();
             max_window = std::max(max_window, window);
-            int slot = 0;
-            for (int i = 0; i < n; ++i) {
-                if (!act[i])
-                    continue;
-                hodmas_chan_entry e;
-                e.a = aa[i];
-                e.d0sq = d0sq[i];
-                e.d0 = d0[i];
-                e.frac0 = fr[i];
-                e.lo = (float)(-(double)T0[i]);
-                e.hi = (float)((double)(S - 1) - (double)T0[i]);
-                e.off = T0[i] - wlo[i] + (slot % chunk) * window;
-                e.channel = i;
-                p->entries.push_back(e);
+            // slots in element order; the LDS window of slot s sits at (s % chunk) * window
+            std::vector<int> slot_elem;
+            for (int i = 0; i < n; ++i)
+                if (act[i])
+                    slot_elem.push_back(i);
+            for (int sl = 0; sl < n_active; ++sl) {
+                const int i = slot_elem[sl];
                 p->stage.push_back(hodmas_stage_entry{i, wlo[i]});
-                ++slot;
+            }
+            // per-element constants: within each chunk, the slots of split group g
+            // (g, g+split, ...) are stored together, so a wave reads them in order
+            for (int c0 = 0; c0 < n_active; c0 += chunk) {
+                const int nch = std::min(chunk, n_active - c0);
+                for (int g = 0; g < split; ++g) {
+                    for (int sl = c0 + g; sl < c0 + nch; sl += split) {
+                        const int i = slot_elem[sl];
+                        hodmas_chan_entry e;
+                        e.a = aa[i];
+                        e.d0sq = d0sq[i];
+                        e.d0 = d0[i];
+                        e.frac0 = fr[i];
+                        e.lo = (float)(-(double)T0[i]);
+                        e.hi = (float)((double)(S - 1) - (double)T0[i]);
+                        e.off = 4 * (T0[i] - wlo[i] + (sl % chunk) * window);
+                        e.channel = i;
+                        p->entries.push_back(e);
+                    }
+                }
             }
         }
     }

@@ -29,11 +29,16 @@ struct FrameArgs {
     float out_scale;         // frame_max: kernel result -> image units
 };
 
-// Work list of the persistent batched kernel (device memory).
+// Work list of the persistent batched kernels (device memory).  Units are
+// grouped by kind = (order, storage type); kind k owns units [begin[k], end[k]).
+constexpr int kBatchKinds = HODMAS_MAX_ORDER * 3;
+constexpr int batch_kind(int order, int dtype) { return (order - 1) * 3 + dtype; }
+
 struct BatchHeader {
     int32_t n_units;
     int32_t n_frames;
-    int32_t pad[2];
+    int32_t begin[kBatchKinds];
+    int32_t end[kBatchKinds];
 };
 
 struct BatchFrame {
@@ -85,9 +90,9 @@ namespace hodmas {
 // Kernel arguments of one frame under `plan`.
 FrameArgs frame_args(const hodmas_plan_s* plan, const void* rf_dev, float* image_dev);
 
-// The persistent batched kernel (for graph nodes) and a direct launch of it.
-const void* batch_kernel(bool compensated);
-int launch_batch(const BatchHeader* hdr, const BatchFrame* frames, const BatchUnit* units, int grid,
-                 bool compensated, int64_t lds_bytes, void* stream);
+// The persistent batched kernel of one kind (for graph nodes) and a launch of it.
+const void* batch_kernel(int order, int dtype, bool compensated);
+int launch_batch(int order, int dtype, const BatchHeader* hdr, const BatchFrame* frames,
+                 const BatchUnit* units, int grid, bool compensated, int64_t lds_bytes, void* stream);
 
 }  // namespace hodmas

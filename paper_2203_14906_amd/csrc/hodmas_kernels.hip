@@ -6,7 +6,7 @@
 //      workgroup staged with coalesced channel-major loads, and interpolates,
 //   3. takes the signed k-th root y = sign(s)|s|^(1/k)       (Eq. 2, Eqs. 4-6),
 //   4. accumulates the power sums p_j = sum y^j, j = 1..k, with compensated
-//      float32 summation,
+//      float32 summation (pairwise groups of four, Kahan steps per 16 elements),
 // and per pixel recovers the order-k symmetric sum e_k from p_1..p_k with
 // Newton's identities (the general form of Eqs. 3, 7, 8 and 9):
 //   e_0 = 1,  m e_m = sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
@@ -49,24 +49,40 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x)
     s = t;
 }
 
-// Delayed, interpolated sample of one element for this lane's pixel.
-template <bool CHECK>
-__device__ __forceinline__ float gather(const hodmas_chan_entry& e, float u2, float q,
-                                        const float* __restrict__ lds)
+// Where one element's delayed sample sits in the LDS window for this lane's
+// pixel: t = delay - floor(anchor delay), its fraction f and the LDS index.
+// d^2 - d0^2 comes from one FMA on per-pixel terms; d - d0 = (d^2 - d0^2)/(d + d0).
+struct Tap {
+    float t, f;
+    int addr;    // LDS byte address of the sample before the delay
+};
+
+__device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, float q)
 {
-    // d^2 - d0^2 for this pixel, then d - d0 = (d^2 - d0^2) / (d + d0)
-    float num = __builtin_fmaf(u2, e.a, q);
-    float d = __builtin_amdgcn_sqrtf(__builtin_fabsf(e.d0sq + num));
-    float r = __builtin_amdgcn_rcpf(d + e.d0);
-    float t = __builtin_fmaf(num, r, e.frac0);      // delay minus floor(anchor delay)
-    float fl = __builtin_floorf(t);
-    float f = t - fl;
-    int idx = (int)fl + e.off;
-    float s0 = lds[idx];
-    float s1 = lds[idx + 1];
-    float v = __builtin_fmaf(f, s1 - s0, s0);
+    Tap p;
+    const float num = __builtin_fmaf(u2, e.a, q);
+    const float d = __builtin_amdgcn_sqrtf(__builtin_fabsf(e.d0sq + num));
+    const float r = __builtin_amdgcn_rcpf(d + e.d0);
+    p.t = __builtin_fmaf(num, r, e.frac0);
+    const float fl = __builtin_floorf(p.t);
+    p.f = p.t - fl;
+    p.addr = ((int)fl << 2) + e.off;
+    return p;
+}
+
+__device__ __forceinline__ float lds_at(const float* __restrict__ lds, int addr)
+{
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + addr);
+}
+
+// Linear interpolation between the two staged samples; outside [0, S-1] the
+// element contributes nothing (only tested in tiles that reach the record ends).
+template <bool CHECK>
+__device__ __forceinline__ float interp(const Tap& p, const hodmas_chan_entry& e, float s0, float s1)
+{
+    float v = __builtin_fmaf(p.f, s1 - s0, s0);
     if (CHECK)
-        v = (t >= e.lo && t <= e.hi) ? v : 0.f;     // outside [0, S-1]: no contribution
+        v = (p.t >= e.lo && p.t <= e.hi) ? v : 0.f;
     return v;
 }
 
@@ -146,44 +162,125 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
     }
 }
 
-template <int K, bool COMP, bool CHECK>
-__device__ __forceinline__ void accumulate_chunk(ConstEntry E, int nch, int g, int split, float u2,
-                                                 float q, const float* __restrict__ lds,
-                                                 float (&s)[K], float (&c)[K])
+// Power-sum accumulation.  Compensated mode: four elements are summed pairwise,
+// four such groups (16 elements) accumulate in a plain float32 partial, and the
+// partial enters the running sum with one Kahan step.  The rounding error then
+// stays at a few units of the partials' magnitude instead of growing with N.
+template <int K>
+__device__ __forceinline__ void flush(float (&s)[K], float (&c)[K], float (&P)[K])
 {
-    int sl = g;
-    for (; sl + 3 * split < nch; sl += 4 * split) {
-        float T[4][K];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const hodmas_chan_entry e = E[sl + m * split];
-            powers<K>(gather<CHECK>(e, u2, q, lds), T[m]);
-        }
+    for (int j = 0; j < K; ++j) {
+        kahan_add(s[j], c[j], P[j]);
+        P[j] = 0.f;
+    }
+}
+
+__device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[4])
+{
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            if (COMP) {
-                // pairwise over the four elements, then one Kahan step
-                kahan_add(s[j], c[j], (T[0][j] + T[1][j]) + (T[2][j] + T[3][j]));
-            } else {
-                s[j] += T[0][j];
-                s[j] += T[1][j];
-                s[j] += T[2][j];
-                s[j] += T[3][j];
-            }
+    for (int m = 0; m < 4; ++m)
+        e[m] = E[m];
+}
+
+// One group of four elements: delays and LDS addresses, the four gathers
+// issued together, the interpolations, then -- once this group's LDS data is
+// in -- the scalar loads of the next group's constants (the LDS/scalar wait
+// counter does not order scalar loads, so issuing them earlier would make
+// this group's waits also wait for them), then roots, powers and the sums.
+template <int K, bool COMP, bool CHECK>
+__device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], float u2, float q,
+                                              const float* __restrict__ lds, float (&s)[K], float (&P)[K],
+                                              bool more, ConstEntry En, hodmas_chan_entry (&en)[4])
+{
+    Tap tp[4];
+    float s0[4], s1[4], v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        tp[m] = locate(e[m], u2, q);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        s0[m] = lds_at(lds, tp[m].addr);
+        s1[m] = lds_at(lds, tp[m].addr + 4);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        v[m] = interp<CHECK>(tp[m], e[m], s0[m], s1[m]);
+    // emits nothing: makes the four samples (hence this group's LDS waits)
+    // complete before the scalar loads below are issued
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]) : "memory");
+    if (more)
+        load_group(En, en);
+    float T[4][K];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        powers<K>(v[m], T[m]);
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (COMP) {
+            P[j] += (T[0][j] + T[1][j]) + (T[2][j] + T[3][j]);
+        } else {
+            s[j] += T[0][j];
+            s[j] += T[1][j];
+            s[j] += T[2][j];
+            s[j] += T[3][j];
         }
     }
-    for (; sl < nch; sl += split) {
-        float T[K];
+}
+
+template <int K, bool COMP>
+__device__ __forceinline__ void after_group(int& groups, float (&s)[K], float (&c)[K], float (&P)[K])
+{
+    if (COMP && (++groups & 3) == 0)
+        flush<K>(s, c, P);
+}
+
+// The n elements of this wave's split group in one staged chunk (their
+// constants stored contiguously), four at a time; two constant sets alternate
+// so nothing is copied between them.
+template <int K, bool COMP, bool CHECK>
+__device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, float q,
+                                                 const float* __restrict__ lds, float (&s)[K], float (&c)[K])
+{
+    float P[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        P[j] = 0.f;
+    int sl = 0;
+    if (n >= 4) {
+        hodmas_chan_entry ea[4], eb[4];
+        load_group(E, ea);
+        int groups = 0;
+        while (true) {
+            const bool more_a = sl + 8 <= n;
+            process_group<K, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
+            after_group<K, COMP>(groups, s, c, P);
+            sl += 4;
+            if (!more_a)
+                break;
+            const bool more_b = sl + 8 <= n;
+            process_group<K, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
+            after_group<K, COMP>(groups, s, c, P);
+            sl += 4;
+            if (!more_b)
+                break;
+        }
+    }
+    for (; sl < n; ++sl) {
         const hodmas_chan_entry e = E[sl];
-        powers<K>(gather<CHECK>(e, u2, q, lds), T);
+        const Tap tp = locate(e, u2, q);
+        float T[K];
+        powers<K>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (COMP)
-                kahan_add(s[j], c[j], T[j]);
+                P[j] += T[j];
             else
                 s[j] += T[j];
         }
     }
+    if (COMP)
+        flush<K>(s, c, P);
 }
 
 // Newton's identities: e_m = (1/m) sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
@@ -250,10 +347,15 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
         __syncthreads();                       // previous readers of the LDS are done
         stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, lane);
         __syncthreads();
+        // this group's elements of the chunk: slots g, g+split, ..., stored together
+        int goff = 0;
+        for (int h = 0; h < g; ++h)
+            goff += (nch - h + A.split - 1) / A.split;
+        const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
         if (td.check)
-            accumulate_chunk<K, COMP, true>(E + c0, nch, g, A.split, u2, q, lds, s, c);
+            accumulate_chunk<K, COMP, true>(E + c0 + goff, ng, u2, q, lds, s, c);
         else
-            accumulate_chunk<K, COMP, false>(E + c0, nch, g, A.split, u2, q, lds, s, c);
+            accumulate_chunk<K, COMP, false>(E + c0 + goff, ng, u2, q, lds, s, c);
     }
 
     if (A.split > 1) {
@@ -302,45 +404,28 @@ __global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
     process_tile<K, DT, COMP>(A, blockIdx.x, lds);
 }
 
-// Persistent form: a fixed grid walks a cost-sorted list of (frame, tile)
-// units of many frames with their own plans, orders and storage types.
-// Workgroup b takes units b, 2G-1-b, 2G+b, ... (a snake over the sorted list,
-// which evens out the per-workgroup cost).  Each tile runs exactly the code the
-// per-frame kernel runs for it, so a frame's image does not depend on the mix.
-template <int DT, bool COMP>
-__device__ __forceinline__ void dispatch_order(const FrameArgs& A, int order, int tile, float* lds)
-{
-    switch (order) {
-    case 1: process_tile<1, DT, COMP>(A, tile, lds); break;
-    case 2: process_tile<2, DT, COMP>(A, tile, lds); break;
-    case 3: process_tile<3, DT, COMP>(A, tile, lds); break;
-    case 4: process_tile<4, DT, COMP>(A, tile, lds); break;
-    case 5: process_tile<5, DT, COMP>(A, tile, lds); break;
-    case 6: process_tile<6, DT, COMP>(A, tile, lds); break;
-    default: break;
-    }
-}
-
-template <bool COMP>
+// Persistent form: one kernel per (order, storage type).  Its fixed grid walks
+// that kind's slice of the batch's work list -- (frame, tile) units of many
+// frames with their own plans, sorted by estimated cost -- with workgroup b
+// taking units b, 2G-1-b, 2G+b, ... (a snake, which evens out the per-workgroup
+// cost).  Each tile runs exactly the code of the per-frame kernel, so a frame's
+// image does not depend on what else is in the batch.
+template <int K, int DT, bool COMP>
 __global__ __launch_bounds__(kBlock) void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                               const BatchFrame* __restrict__ frames,
                                                               const BatchUnit* __restrict__ units)
 {
     extern __shared__ float lds[];
-    const int n = hdr->n_units;
+    constexpr int kind = batch_kind(K, DT);
+    const int first = hdr->begin[kind];
+    const int n = hdr->end[kind] - first;
     const int G = gridDim.x;
     for (int r = 0; r * G < n; ++r) {
         const int u = (r & 1) ? (r + 1) * G - 1 - (int)blockIdx.x : r * G + (int)blockIdx.x;
         if (u >= n)
             continue;
-        const BatchUnit un = units[u];
-        const BatchFrame& fr = frames[un.frame];
-        switch (fr.dtype) {
-        case HODMAS_F32: dispatch_order<HODMAS_F32, COMP>(fr.args, fr.order, un.tile, lds); break;
-        case HODMAS_F16: dispatch_order<HODMAS_F16, COMP>(fr.args, fr.order, un.tile, lds); break;
-        case HODMAS_I16: dispatch_order<HODMAS_I16, COMP>(fr.args, fr.order, un.tile, lds); break;
-        default: break;
-        }
+        const BatchUnit un = units[first + u];
+        process_tile<K, DT, COMP>(frames[un.frame].args, un.tile, lds);
     }
 }
 
@@ -383,23 +468,46 @@ int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, int
     return (int)hipErrorInvalidValue;
 }
 
-const void* batch_kernel(bool compensated)
+template <int K, int DT>
+const void* batch_fn(bool comp)
 {
-    return compensated ? reinterpret_cast<const void*>(&hodmas_batch_kernel<true>)
-                       : reinterpret_cast<const void*>(&hodmas_batch_kernel<false>);
+    return comp ? reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, true>)
+                : reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, false>);
 }
 
-int launch_batch(const BatchHeader* hdr, const BatchFrame* frames, const BatchUnit* units, int grid,
-                 bool compensated, int64_t lds_bytes, void* stream)
+template <int DT>
+const void* batch_fn_dt(int order, bool comp)
 {
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (compensated)
-        hipLaunchKernelGGL((hodmas_batch_kernel<true>), dim3(grid), dim3(kBlock), (size_t)lds_bytes, st,
-                           hdr, frames, units);
-    else
-        hipLaunchKernelGGL((hodmas_batch_kernel<false>), dim3(grid), dim3(kBlock), (size_t)lds_bytes, st,
-                           hdr, frames, units);
-    return (int)hipGetLastError();
+    switch (order) {
+    case 1: return batch_fn<1, DT>(comp);
+    case 2: return batch_fn<2, DT>(comp);
+    case 3: return batch_fn<3, DT>(comp);
+    case 4: return batch_fn<4, DT>(comp);
+    case 5: return batch_fn<5, DT>(comp);
+    case 6: return batch_fn<6, DT>(comp);
+    }
+    return nullptr;
+}
+
+const void* batch_kernel(int order, int dtype, bool compensated)
+{
+    switch (dtype) {
+    case HODMAS_F32: return batch_fn_dt<HODMAS_F32>(order, compensated);
+    case HODMAS_F16: return batch_fn_dt<HODMAS_F16>(order, compensated);
+    case HODMAS_I16: return batch_fn_dt<HODMAS_I16>(order, compensated);
+    }
+    return nullptr;
+}
+
+int launch_batch(int order, int dtype, const BatchHeader* hdr, const BatchFrame* frames,
+                 const BatchUnit* units, int grid, bool compensated, int64_t lds_bytes, void* stream)
+{
+    const void* fn = batch_kernel(order, dtype, compensated);
+    if (!fn)
+        return (int)hipErrorInvalidValue;
+    void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
+    return (int)hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, (size_t)lds_bytes,
+                                static_cast<hipStream_t>(stream));
 }
 
 }  // namespace hodmas

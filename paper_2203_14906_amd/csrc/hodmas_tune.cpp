@@ -1,0 +1,154 @@
+// Autotuner: times candidate tilings (tile shape, element split, LDS chunk) of
+// a plan on the current device and keeps the fastest, cached in a JSON-lines
+// file keyed by architecture, geometry, grid, RF layout, order and flags.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hodmas_internal.h"
+
+namespace {
+
+std::string tune_key(const char* arch, const hodmas_geometry* g, const hodmas_grid* gr,
+                     const hodmas_rf_desc* rf, int32_t order, uint32_t flags)
+{
+    // element positions enter through a checksum of their bits
+    unsigned long long h = 1469598103934665603ull;
+    if (g->element_x_m) {
+        for (int i = 0; i < g->n_elements; ++i) {
+            unsigned long long b;
+            std::memcpy(&b, &g->element_x_m[i], sizeof(b));
+            h = (h ^ b) * 1099511628211ull;
+        }
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf),
+                  "%s|n%d|p%.9g|c%.9g|fs%.9g|t0%.9g|x%016llx|g%dx%d|x0%.9g|dx%.9g|z0%.9g|dz%.9g|"
+                  "dt%d|S%d|st%lld|k%d|f%u",
+                  arch, g->n_elements, g->pitch_m, g->sound_speed_m_s, g->fs_hz, g->t0_s, h, gr->nx,
+                  gr->nz, gr->x0_m, gr->dx_m, gr->z0_m, gr->dz_m, rf->dtype, rf->n_samples,
+                  (long long)rf->channel_stride, order, (unsigned)(flags & HODMAS_FLAG_ACC_PLAIN));
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, hodmas_tiling* out)
+{
+    if (!path)
+        return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    char line[1024];
+    bool found = false;
+    const std::string want = "{\"key\": \"" + key + "\", \"tiling\": [";
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::strncmp(line, want.c_str(), want.size()) != 0)
+            continue;
+        hodmas_tiling t;
+        if (std::sscanf(line + want.size(), "%d, %d, %d, %d", &t.tile_x, &t.tile_z, &t.split, &t.chunk) == 4) {
+            *out = t;  // the last entry for a key wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, const hodmas_tiling& t, double us)
+{
+    if (!path)
+        return;
+    FILE* f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f, "{\"key\": \"%s\", \"tiling\": [%d, %d, %d, %d], \"us\": %.3f}\n", key.c_str(), t.tile_x,
+                 t.tile_z, t.split, t.chunk, us);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const hodmas_grid* grid,
+                                         const hodmas_rf_desc* rf, int32_t order, uint32_t flags,
+                                         const char* cache_path, hodmas_tiling* out)
+{
+    if (!geometry || !grid || !rf || !out || order < 1 || order > HODMAS_MAX_ORDER)
+        return HODMAS_EINVAL;
+    if (flags & HODMAS_FLAG_HOST_ONLY)
+        return HODMAS_EINVAL;
+    int dev = -1;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return HODMAS_EDEVICE;
+    const std::string key = tune_key(prop.gcnArchName, geometry, grid, rf, order, flags);
+    if (cache_lookup(cache_path, key, out))
+        return HODMAS_OK;
+
+    static const hodmas_tiling kCandidates[] = {
+        {16, 16, 1, 64}, {16, 16, 1, 128}, {32, 8, 1, 64}, {8, 32, 1, 64},
+        {16, 8, 2, 64},  {16, 8, 2, 128},  {8, 8, 4, 64},  {8, 8, 4, 128},
+    };
+    const size_t esz = rf->dtype == HODMAS_F32 ? 4 : 2;
+    const size_t rf_bytes = esz * (size_t)rf->channel_stride * (size_t)geometry->n_elements;
+    const size_t img_bytes = 4 * (size_t)grid->nx * (size_t)grid->nz;
+    void* d_rf = nullptr;
+    float* d_img = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+        if (d_rf) (void)hipFree(d_rf);
+        if (d_img) (void)hipFree(d_img);
+    };
+    // timing does not depend on sample values: a zero record suffices
+    if (hipMalloc(&d_rf, rf_bytes) != hipSuccess || hipMalloc((void**)&d_img, img_bytes) != hipSuccess ||
+        hipMemset(d_rf, 0, rf_bytes) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return HODMAS_ENOMEM;
+    }
+    double best_us = 1e300;
+    hodmas_tiling best{};
+    for (const hodmas_tiling& cand : kCandidates) {
+        hodmas_plan_t p = nullptr;
+        if (hodmas_plan(geometry, grid, rf, order, flags & ~HODMAS_FLAG_HOST_ONLY, &cand, &p) != HODMAS_OK)
+            continue;
+        bool ok = true;
+        for (int w = 0; w < 2 && ok; ++w)
+            ok = hodmas_beamform(p, d_rf, order, d_img, st) == HODMAS_OK;
+        std::vector<float> times;
+        for (int r = 0; r < 5 && ok; ++r) {
+            ok = hipEventRecord(e0, st) == hipSuccess &&
+                 hodmas_beamform(p, d_rf, order, d_img, st) == HODMAS_OK &&
+                 hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+                times.push_back(ms);
+        }
+        if (ok && hipStreamSynchronize(st) != hipSuccess)
+            ok = false;
+        hodmas_plan_info inf;
+        if (ok && !times.empty() && hodmas_plan_get_info(p, &inf) == HODMAS_OK) {
+            std::sort(times.begin(), times.end());
+            const double us = 1e3 * times[times.size() / 2];
+            if (us < best_us) {
+                best_us = us;
+                best = inf.tiling;   // the chunk may have been reduced to fit LDS
+            }
+        }
+        (void)hodmas_destroy(p);
+    }
+    cleanup();
+    if (best_us >= 1e300)
+        return HODMAS_EUNSUPPORTED;
+    *out = best;
+    cache_store(cache_path, key, best, best_us);
+    return HODMAS_OK;
+}

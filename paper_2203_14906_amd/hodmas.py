@@ -120,6 +120,9 @@ def _load():
     L.hodmas_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     L.hodmas_batch_destroy.restype = i32
     L.hodmas_batch_destroy.argtypes = [vp]
+    L.hodmas_autotune.restype = i32
+    L.hodmas_autotune.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Grid), ctypes.POINTER(RfDesc),
+                                  i32, u32, ctypes.c_char_p, ctypes.POINTER(Tiling)]
     L.hodmas_version.restype = ctypes.c_char_p
     L.hodmas_version.argtypes = []
     return L
@@ -148,6 +151,35 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _c_structs(geometry, grid, n_samples, dtype, dequant_scale, frame_max, channel_stride):
+    n = int(geometry.n_elements)
+    ex = getattr(geometry, "element_x_m", None)
+    keep = None
+    g = Geometry(n, float(geometry.pitch_m), float(geometry.sound_speed_m_s), float(geometry.fs_hz),
+                 float(geometry.t0_s), None)
+    if ex is not None:
+        keep = (ctypes.c_double * n)(*[float(v) for v in ex])
+        g.element_x_m = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    gr = Grid(int(grid.nx), int(grid.nz), float(grid.x0_m), float(grid.dx_m), float(grid.z0_m),
+              float(grid.dz_m))
+    dt = _DTYPE_NAMES[dtype] if isinstance(dtype, str) else int(dtype)
+    stride = int(channel_stride if channel_stride is not None else n_samples)
+    rd = RfDesc(dt, int(n_samples), stride, float(dequant_scale), float(frame_max))
+    return g, gr, rd, keep
+
+
+def autotune(geometry, grid, n_samples, dtype="f32", order=6, *, dequant_scale=1.0, frame_max=0.0,
+             channel_stride=None, flags=0, cache_path=None):
+    """Fastest tiling (tile_x, tile_z, split, chunk) for this plan and order,
+    measured on the current device (see hodmas_autotune)."""
+    g, gr, rd, keep = _c_structs(geometry, grid, n_samples, dtype, dequant_scale, frame_max, channel_stride)
+    t = Tiling()
+    _check(lib.hodmas_autotune(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), int(order), int(flags),
+                               cache_path.encode() if cache_path else None, ctypes.byref(t)),
+           "hodmas_autotune")
+    return (t.tile_x, t.tile_z, t.split, t.chunk)
 
 
 class Plan:

@@ -1,0 +1,35 @@
+"""Autotuner on the GPU: picks a valid tiling, caches it, and the tuned plan
+keeps parity with the oracle."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2203_14906_amd import phantom as ph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_cache_and_parity(tmp_path):
+    assert torch.cuda.is_available()
+    from paper_2203_14906_amd import hodmas
+    f = ph.config_frame(1)
+    cache = str(tmp_path / "tune.jsonl")
+    t0 = time.perf_counter()
+    til = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 4, cache_path=cache)
+    first = time.perf_counter() - t0
+    tx, tz, split, chunk = til
+    assert tx * tz * split == 256 and split in (1, 2, 4) and chunk >= 1
+    assert os.path.exists(cache) and til == tuple(__import__("json").loads(open(cache).readline())["tiling"])
+    t0 = time.perf_counter()
+    again = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 4, cache_path=cache)
+    assert again == til and time.perf_counter() - t0 < first
+    plan = hodmas.Plan(f.geometry, f.grid, 1024, "f32", max_order=4, tiling=til)
+    arr = ph.to_fp32(f.rf)
+    img = plan.beamform(torch.from_numpy(arr).cuda(), 4).cpu().numpy().astype(np.float64)
+    ref = O.beamform(arr, f.geometry, f.grid, 4)
+    assert np.linalg.norm(img - ref) / np.linalg.norm(ref) <= 1e-5
+    plan.close()

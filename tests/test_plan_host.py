@@ -109,7 +109,8 @@ def test_tables_cover_every_delay(case):
         ixs, izs = np.meshgrid(np.arange(td.ix0, td.ix0 + td.nx), np.arange(td.iz0, td.iz0 + td.nz))
         ixs, izs = ixs.ravel(), izs.ravel()
         t = _exact_delays(ex, grid, t0s, ixs, izs)                     # [pixels, elements]
-        active = [e.channel for e in entries[td.first_entry:td.first_entry + td.n_active]]
+        active = [st.channel for st in stage[td.first_entry:td.first_entry + td.n_active]]
+        assert active == sorted(active)
         for i in range(len(ex)):
             if i not in active:                                        # skipped: never in the record
                 assert np.all((t[:, i] < 0) | (t[:, i] > S - 1)), (td.ix0, td.iz0, i)
@@ -125,16 +126,26 @@ def test_tables_cover_every_delay(case):
         w = (grid.z0_m + izs * grid.dz_m) / LAM - td.za
         u2 = (2.0 * u).astype(np.float32)
         q = (u * u + w * (w + 2.0 * td.za)).astype(np.float32)
+        tile_entries = entries[td.first_entry:td.first_entry + td.n_active]
+        by_elem = {e.channel: e for e in tile_entries}
+        assert len(by_elem) == td.n_active
+        # constants of each chunk are grouped by split group: slots g, g+split, ...
+        split = info.tiling.split
+        order = []
+        for c0 in range(0, td.n_active, chunk):
+            nch = min(chunk, td.n_active - c0)
+            for gq in range(split):
+                order += list(range(c0 + gq, c0 + nch, split))
+        assert [e.channel for e in tile_entries] == [stage[td.first_entry + sl].channel for sl in order]
         for slot in range(td.n_active):
-            e = entries[td.first_entry + slot]
             st = stage[td.first_entry + slot]
-            i = e.channel
-            assert st.channel == i
+            i = st.channel
+            e = by_elem[i]
             T0 = int(round(-e.lo))
             assert e.hi == pytest.approx(S - 1 - T0, abs=0)
             ta = math.sqrt((td.xa - ex[i] / LAM) ** 2 + td.za ** 2) - t0s
             assert T0 == math.floor(ta) and e.frac0 == pytest.approx(ta - T0, abs=1e-6)
-            assert e.off == T0 - st.first_sample + (slot % chunk) * td.window
+            assert e.off == 4 * (T0 - st.first_sample + (slot % chunk) * td.window)
             # float32 reconstruction of each pixel's delay, as the kernel forms it
             num = (u2.astype(np.float64) * np.float64(e.a) + q).astype(np.float32)
             d = np.sqrt(np.abs(np.float64(e.d0sq) + num)).astype(np.float32)
@@ -178,3 +189,16 @@ def test_batch_argument_validation_without_device():
     assert L.hodmas_batch_replay(None, None) == hodmas.EINVAL
     assert L.hodmas_batch_capture(None) == hodmas.EINVAL
     assert L.hodmas_batch_set(None, None, None, None, None, 1, None) == hodmas.EINVAL
+
+
+def test_autotune_argument_validation_without_device():
+    L = hodmas.lib
+    t = hodmas.Tiling()
+    g = hodmas.Geometry(8, 0.3e-3, 1540.0, 40e6, 0.0, None)
+    gr = hodmas.Grid(8, 8, -1e-3, 0.3e-3, 1e-3, 0.3e-3)
+    rd = hodmas.RfDesc(0, 128, 128, 1.0, 0.0)
+    assert L.hodmas_autotune(None, ctypes.byref(gr), ctypes.byref(rd), 1, 0, None, ctypes.byref(t)) == hodmas.EINVAL
+    assert L.hodmas_autotune(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), 7, 0, None, ctypes.byref(t)) == hodmas.EINVAL
+    assert L.hodmas_autotune(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), 1, hodmas.FLAG_HOST_ONLY, None,
+                             ctypes.byref(t)) == hodmas.EINVAL
+    assert L.hodmas_autotune(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), 1, 0, None, None) == hodmas.EINVAL
