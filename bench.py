@@ -32,6 +32,10 @@ SLOTS = {1: 19, 2: 25, 3: 32, 4: 32, 5: 36, 6: 38}
 # 157.3 TFLOP/s FP32 vector (published) = 78.6e12 FMA lane-slots/s
 # (256 CUs x 128 FP32 lanes/clock x 2.4 GHz).
 VALU_PEAK_TSLOT = 78.64
+# The all-orders kernel computes the delay and interpolation once (18 slots),
+# the roots of every order from shared transcendentals, and one add per
+# distinct power sum (1, 3, 5, 8, 12, 15 sums for orders up to 1..6).
+FUSED_SLOTS = {1: 19, 2: 26, 3: 38, 4: 47, 5: 59, 6: 68}
 
 
 def parse():
@@ -125,6 +129,31 @@ def bench_plain(args, torch):
     dom = max(orders, key=lambda k: per_order_ms[k])
     achieved = SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
 
+    # every order 1..kmax from one launch per frame
+    fused = None
+    kmax = max(orders)
+    if sorted(orders) == list(range(1, kmax + 1)):
+        outs_all = [[torch.empty((grid.nz, grid.nx), dtype=torch.float32, device=dev) for _ in orders]
+                    for _ in frames]
+        for _ in range(args.warmup):
+            for b in range(args.batch):
+                plan.beamform_orders(rf_dev[b], kmax, outs_all[b], stream=stream)
+        fev = _events(torch, args.steps)
+        torch.cuda.synchronize()
+        for s in range(args.steps):
+            fev[s][0].record(stream)
+            for b in range(args.batch):
+                plan.beamform_orders(rf_dev[b], kmax, outs_all[b], stream=stream)
+            fev[s][1].record(stream)
+        torch.cuda.synchronize()
+        f_ms = sum(a.elapsed_time(z) for a, z in fev) / (args.steps * args.batch)
+        f_ach = FUSED_SLOTS[kmax] * pixch / (f_ms * 1e-3) / 1e12
+        fused = {"kernel": "hodmas_orders_kernel<%d, f32>" % kmax, "kernel_us_per_frame": round(f_ms * 1e3, 2),
+                 "gpixch_s_sum_orders": round(pixch * len(orders) / (f_ms * 1e-3) / 1e9, 2),
+                 "speedup_vs_per_order_launches": round(sum(per_order_ms.values()) / f_ms, 3),
+                 "slots_per_pixch": FUSED_SLOTS[kmax], "achieved_tslot_s": round(f_ach, 2),
+                 "frac": round(f_ach / VALU_PEAK_TSLOT, 4)}
+
     # relative L2 of the last images against the oracle is checked by the tests;
     # here only the CPU oracle's throughput on the same batch is measured.
     cpu = None
@@ -164,6 +193,7 @@ def bench_plain(args, torch):
                    "tiling": [info.tiling.tile_x, info.tiling.tile_z, info.tiling.split, info.tiling.chunk]},
         "per_order_gpixch_s": per_order,
         "per_order_kernel_us": {str(k): round(per_order_ms[k] * 1e3, 2) for k in orders},
+        "fused_all_orders": fused,
         "roofline": {"bound": "alu", "kernel": "hodmas_frame_kernel<%d, f32>" % dom,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),

@@ -71,6 +71,7 @@ typedef enum {
 #define HODMAS_FLAG_ACC_PLAIN   0x1u  /* plain float32 power sums (default: compensated) */
 #define HODMAS_FLAG_HOST_ONLY   0x2u  /* build host tables only; no device use (inspection) */
 #define HODMAS_FLAG_FORCE_CHECK 0x4u  /* always run the record-boundary test per sample */
+#define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts */
 
 /* Linear array.  element_x_m == NULL means a centred uniform array,
  * x_i = (i - (n_elements-1)/2) * pitch_m.  The pointer is read during
@@ -103,12 +104,14 @@ typedef struct {
     float frame_max;             /* >= 0; 0 means 1 */
 } hodmas_rf_desc;
 
-/* Tiling of a plan.  Zero fields are chosen by the library. */
+/* Tiling of a plan.  Zero fields are chosen by the library.  A workgroup has
+ * tile_x * tile_z * split threads, which must be 256 or 512 (plans used in a
+ * batch need 256). */
 typedef struct {
     int32_t tile_x;              /* pixels per tile along x */
     int32_t tile_z;              /* pixels per tile along z */
-    int32_t split;               /* waves sharing one pixel's channels: 1, 2 or 4 */
-    int32_t chunk;               /* channels staged in LDS at a time */
+    int32_t split;               /* wave groups sharing one pixel's elements: 1, 2 or 4 */
+    int32_t chunk;               /* elements staged in LDS at a time */
 } hodmas_tiling;
 
 typedef struct hodmas_plan_s* hodmas_plan_t;
@@ -135,6 +138,18 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
  * EUNSUPPORTED (order outside [1, min(6, max_order)]), EDEVICE (launch). */
 hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t order,
                               float* image_dev, void* stream);
+
+/* Beamform one frame at every order 1..max_order in a single pass: the delays,
+ * gathers and interpolated samples are shared by all orders and the roots
+ * share their transcendentals (the paper compares DAS, DMAS and DMAS-3..5 on
+ * the same data, Table II).  images_dev: host array of max_order device
+ * pointers; images_dev[k-1] (float32 [nz][nx]) receives order k, each fully
+ * overwritten.  Results agree with hodmas_beamform to the same tolerance
+ * (the roots are formed along different but equivalent routes).  One launch,
+ * asynchronous, no allocation.  Errors as for hodmas_beamform; EUNSUPPORTED
+ * also when the combination of all power sums would not fit the LDS. */
+hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int32_t max_order,
+                                     float* const* images_dev, void* stream);
 
 /* Release a plan and its device tables.  NULL is accepted.  The caller must
  * not destroy a plan while work launched with it may still be running. */
@@ -228,7 +243,7 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
  * copied to the device asynchronously on `stream` (launches on the same stream
  * see it).  Errors: EINVAL (null entries, order outside the plan, plan flags,
  * host-only or other-device plan, too many frames/units, plan LDS above the
- * batch's bound), EUNSUPPORTED, EDEVICE. */
+ * batch's bound or a workgroup other than 256 threads), EUNSUPPORTED, EDEVICE. */
 hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
                                const void* const* rf, const int32_t* orders,
                                float* const* images, int32_t n_frames, void* stream);

@@ -165,6 +165,8 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
                 return HODMAS_EUNSUPPORTED;
             if (p->lds_bytes > b->lds_bytes)
                 return HODMAS_EINVAL;
+            if (p->tiling.tile_x * p->tiling.tile_z * p->tiling.split != hodmas::kBlock)
+                return HODMAS_EINVAL;   // the persistent kernels run 256-thread tiles
             if ((int64_t)(units.size() + p->tiles.size()) > b->max_units)
                 return HODMAS_EINVAL;
             pixch += int64_t(p->grid.nx) * p->grid.nz * p->geom.n_elements;

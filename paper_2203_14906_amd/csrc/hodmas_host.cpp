@@ -74,7 +74,8 @@ hodmas_status validate(const hodmas_geometry* g, const hodmas_grid* gr, const ho
                 return HODMAS_EINVAL;
             if (t->split != 1 && t->split != 2 && t->split != 4)
                 return HODMAS_EINVAL;
-            if (int64_t(t->tile_x) * t->tile_z * t->split != hodmas::kBlock)
+            const int64_t block = int64_t(t->tile_x) * t->tile_z * t->split;
+            if (block != hodmas::kBlock && block != hodmas::kMaxBlock)
                 return HODMAS_EINVAL;
         }
     }
@@ -305,7 +306,8 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         return st;
     }
     // LDS: `chunk` windows of `max_window` floats; shrink the chunk until it fits.
-    const int64_t reduce_bytes = int64_t(hodmas::kBlock / p->tiling.split) * (p->tiling.split - 1) *
+    const int64_t block = int64_t(p->tiling.tile_x) * p->tiling.tile_z * p->tiling.split;
+    const int64_t reduce_bytes = int64_t(block / p->tiling.split) * (p->tiling.split - 1) *
                                  HODMAS_MAX_ORDER * 2 * 4;
     const int64_t cap = 64 * 1024;
     if (int64_t(p->max_window) * 4 > hodmas::kMaxLdsBytes) {
@@ -355,6 +357,7 @@ FrameArgs hodmas::frame_args(const hodmas_plan_s* plan, const void* rf_dev, floa
     a.split = plan->tiling.split;
     a.chunk = plan->tiling.chunk;
     a.n_tiles = (int32_t)plan->tiles.size();
+    a.block = plan->tiling.tile_x * plan->tiling.tile_z * plan->tiling.split;
     a.x0s = plan->x0s;
     a.dxs = plan->dxs;
     a.z0s = plan->z0s;
@@ -383,6 +386,41 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
     const FrameArgs a = hodmas::frame_args(plan, rf_dev, image_dev);
     const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
     int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, plan->lds_bytes, stream);
+    if (cur != plan->device)
+        (void)hipSetDevice(cur);
+    return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
+}
+
+hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int32_t max_order,
+                                     float* const* images_dev, void* stream)
+{
+    if (!plan || plan->magic != kMagic || !rf_dev || !images_dev)
+        return HODMAS_EINVAL;
+    if (plan->flags & HODMAS_FLAG_HOST_ONLY)
+        return HODMAS_EINVAL;
+    if (max_order < 1 || max_order > plan->max_order || max_order > HODMAS_MAX_ORDER)
+        return HODMAS_EUNSUPPORTED;
+    hodmas::OrderImages out{};
+    for (int k = 0; k < max_order; ++k) {
+        if (!images_dev[k])
+            return HODMAS_EINVAL;
+        out.img[k] = images_dev[k];
+    }
+    // LDS: the staged windows, or the cross-group combination of the power sums
+    const int64_t nt = hodmas::kOrderSums;
+    const int64_t block = int64_t(plan->tiling.tile_x) * plan->tiling.tile_z * plan->tiling.split;
+    const int64_t reduce = block / plan->tiling.split * (plan->tiling.split - 1) * 2 * nt * 4;
+    const int64_t lds = std::max<int64_t>(int64_t(plan->tiling.chunk) * plan->max_window * 4, reduce);
+    if (lds > 64 * 1024)
+        return HODMAS_EUNSUPPORTED;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return HODMAS_EDEVICE;
+    if (cur != plan->device && hipSetDevice(plan->device) != hipSuccess)
+        return HODMAS_EDEVICE;
+    const FrameArgs a = hodmas::frame_args(plan, rf_dev, nullptr);
+    const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
+    int rc = hodmas::launch_orders(a, out, max_order, plan->rf.dtype, comp, lds, stream);
     if (cur != plan->device)
         (void)hipSetDevice(cur);
     return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;

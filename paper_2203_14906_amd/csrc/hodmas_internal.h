@@ -8,8 +8,11 @@
 
 namespace hodmas {
 
-constexpr int kBlock = 256;                 // threads per workgroup (4 wave64)
+constexpr int kBlock = 256;                 // threads per workgroup of the batched kernels
+constexpr int kMaxBlock = 512;              // per-frame kernel: 256 or 512 threads
 constexpr int64_t kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+// distinct power sums behind orders 1..6 in the all-orders kernel
+constexpr int kOrderSums = 15;
 
 // Everything one launch over one frame needs, passed by value as kernel
 // arguments.  Positions are in samples of one-way flight (metres * fs / c).
@@ -24,9 +27,15 @@ struct FrameArgs {
     int32_t nx, nz;
     int32_t tile_x, split, chunk;
     int32_t n_tiles;
+    int32_t block;           // threads per workgroup: tile_x * tile_z * split
     double x0s, dxs, z0s, dzs;  // grid in samples
     float in_scale;          // stored value -> kernel value (dequant / frame_max)
     float out_scale;         // frame_max: kernel result -> image units
+};
+
+// Output images of the all-orders kernel: img[k-1] receives order k.
+struct OrderImages {
+    float* img[HODMAS_MAX_ORDER];
 };
 
 // Work list of the persistent batched kernels (device memory).  Units are
@@ -89,6 +98,10 @@ namespace hodmas {
 
 // Kernel arguments of one frame under `plan`.
 FrameArgs frame_args(const hodmas_plan_s* plan, const void* rf_dev, float* image_dev);
+
+// Orders 1..kmax of one frame in one pass.
+int launch_orders(const FrameArgs& a, const OrderImages& out, int kmax, int dtype, bool compensated,
+                  int64_t lds_bytes, void* stream);
 
 // The persistent batched kernel of one kind (for graph nodes) and a launch of it.
 const void* batch_kernel(int order, int dtype, bool compensated);

@@ -127,19 +127,19 @@ __device__ __forceinline__ void powers(float v, float (&T)[K])
 
 template <int DT>
 __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, int nch, int window,
-                                            float* __restrict__ lds, int wave, int lane)
+                                            float* __restrict__ lds, int wave, int nwaves, int lane)
 {
     using T = typename Storage<DT>::T;
     const T* __restrict__ rf = static_cast<const T*>(A.rf);
     for (int base = 0; base < window; base += 64) {
         const int i = base + lane;
         int c = wave;
-        // four channels per pass so four loads are in flight per lane
-        for (; c + 12 < nch; c += 16) {
+        // four elements per pass so four loads are in flight per lane
+        for (; c + 3 * nwaves < nch; c += 4 * nwaves) {
             float v[4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const hodmas_stage_entry se = st[c + 4 * m];
+                const hodmas_stage_entry se = st[c + m * nwaves];
                 const int t = se.first_sample + i;
                 v[m] = 0.f;
                 if (i < window && t >= 0 && t < A.n_samples)
@@ -148,9 +148,9 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
 #pragma unroll
             for (int m = 0; m < 4; ++m)
                 if (i < window)
-                    lds[(c + 4 * m) * window + i] = v[m];
+                    lds[(c + m * nwaves) * window + i] = v[m];
         }
-        for (; c < nch; c += 4) {
+        for (; c < nch; c += nwaves) {
             const hodmas_stage_entry se = st[c];
             const int t = se.first_sample + i;
             float v = 0.f;
@@ -310,7 +310,8 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
 {
     const hodmas_tile_desc td = ConstTile(A.tiles)[tile];
     const int tid = threadIdx.x;
-    const int npix = kBlock / A.split;
+    const int npix = A.block / A.split;
+    const int nwaves = A.block >> 6;
     const int g = __builtin_amdgcn_readfirstlane(tid / npix);   // npix is a multiple of 64
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -345,7 +346,7 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();                       // previous readers of the LDS are done
-        stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, lane);
+        stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
         // this group's elements of the chunk: slots g, g+split, ..., stored together
         int goff = 0;
@@ -398,7 +399,7 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
 }
 
 template <int K, int DT, bool COMP>
-__global__ __launch_bounds__(kBlock) void hodmas_frame_kernel(FrameArgs A)
+__global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 {
     extern __shared__ float lds[];
     process_tile<K, DT, COMP>(A, blockIdx.x, lds);
@@ -429,10 +430,323 @@ __global__ __launch_bounds__(kBlock) void hodmas_batch_kernel(const BatchHeader*
     }
 }
 
+// ---------------------------------------------------------------------------
+// Every order 1..KMAX in one pass.  The delay, gather and interpolation are
+// the same for all orders; the roots share their transcendentals
+// (|v|^(1/4) = sqrt(|v|^(1/2)), |v|^(1/6) = sqrt(|v|^(1/3)), one log2 serves
+// the cube and fifth roots); and many power sums coincide across orders,
+// since y_k^j = sign(v)^j |v|^(j/k) depends only on j/k and the parity of j:
+// orders 1..6 need 15 distinct sums instead of 21.
+//
+//   sum   exponent  signed   used as p_j of order k
+//    0      1        yes     k1 p1, k3 p3, k5 p5
+//    1      1        no      k2 p2, k4 p4, k6 p6
+//    2      1/2      yes     k2 p1, k6 p3
+//    3      1/2      no      k4 p2
+//    4      1/3      yes     k3 p1
+//    5      1/3      no      k6 p2
+//    6      2/3      no      k3 p2, k6 p4
+//    7      1/4      yes     k4 p1
+//    8      3/4      yes     k4 p3
+//    9..12  j/5      j odd   k5 p1..p4
+//   13      1/6      yes     k6 p1
+//   14      5/6      yes     k6 p5
+constexpr int kSums = kOrderSums;
+constexpr int kSumOf[HODMAS_MAX_ORDER + 1][HODMAS_MAX_ORDER] = {
+    {0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0},
+    {2, 1, 0, 0, 0, 0},
+    {4, 6, 0, 0, 0, 0},
+    {7, 3, 8, 1, 0, 0},
+    {9, 10, 11, 12, 0, 0},
+    {13, 5, 2, 6, 14, 1},
+};
+
+// Is sum i needed by some order <= KMAX?
+constexpr bool sum_needed(int i, int kmax)
+{
+    for (int k = 1; k <= kmax; ++k)
+        for (int j = 0; j < k; ++j)
+            if (kSumOf[k][j] == i)
+                return true;
+    return false;
+}
+
+template <int KMAX>
+__device__ __forceinline__ void terms_all(float v, float (&T)[kSums])
+{
+    const float a = __builtin_fabsf(v);
+    T[0] = v;
+    T[1] = a;
+    if constexpr (KMAX >= 2) {
+        const float r2 = __builtin_amdgcn_sqrtf(a);
+        T[2] = __builtin_copysignf(r2, v);
+        T[3] = r2;
+        if constexpr (KMAX >= 3) {
+            const float L = __builtin_amdgcn_logf(a);
+            const float r3 = __builtin_amdgcn_exp2f(L * (1.0f / 3));
+            T[4] = __builtin_copysignf(r3, v);
+            T[5] = r3;
+            T[6] = r3 * r3;
+            if constexpr (KMAX >= 4) {
+                const float y4 = __builtin_copysignf(__builtin_amdgcn_sqrtf(r2), v);
+                T[7] = y4;
+                T[8] = y4 * r2;
+                if constexpr (KMAX >= 5) {
+                    const float r5 = __builtin_amdgcn_exp2f(L * 0.2f);
+                    const float y5 = __builtin_copysignf(r5, v);
+                    const float q5 = r5 * r5;
+                    T[9] = y5;
+                    T[10] = q5;
+                    T[11] = y5 * q5;
+                    T[12] = q5 * q5;
+                    if constexpr (KMAX >= 6) {
+                        const float y6 = __builtin_copysignf(__builtin_amdgcn_sqrtf(r3), v);
+                        T[13] = y6;
+                        T[14] = y6 * T[6];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int KMAX, bool COMP, bool CHECK>
+__device__ __forceinline__ void process_group_all(const hodmas_chan_entry (&e)[4], float u2, float q,
+                                                  const float* __restrict__ lds, float (&s)[kSums],
+                                                  float (&P)[kSums], bool more, ConstEntry En,
+                                                  hodmas_chan_entry (&en)[4])
+{
+    Tap tp[4];
+    float s0[4], s1[4], v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        tp[m] = locate(e[m], u2, q);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        s0[m] = lds_at(lds, tp[m].addr);
+        s1[m] = lds_at(lds, tp[m].addr + 4);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        v[m] = interp<CHECK>(tp[m], e[m], s0[m], s1[m]);
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]) : "memory");
+    if (more)
+        load_group(En, en);
+    // two elements at a time keep the live term count at 2 * kSums
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        float Ta[kSums], Tb[kSums];
+        terms_all<KMAX>(v[2 * h], Ta);
+        terms_all<KMAX>(v[2 * h + 1], Tb);
+#pragma unroll
+        for (int j = 0; j < kSums; ++j) {
+            if (!sum_needed(j, KMAX))
+                continue;
+            if (COMP) {
+                P[j] += Ta[j] + Tb[j];
+            } else {
+                s[j] += Ta[j];
+                s[j] += Tb[j];
+            }
+        }
+    }
+}
+
+template <int KMAX, bool COMP>
+__device__ __forceinline__ void flush_all(float (&s)[kSums], float (&c)[kSums], float (&P)[kSums])
+{
+#pragma unroll
+    for (int j = 0; j < kSums; ++j) {
+        if (!sum_needed(j, KMAX))
+            continue;
+        kahan_add(s[j], c[j], P[j]);
+        P[j] = 0.f;
+    }
+}
+
+template <int KMAX, bool COMP, bool CHECK>
+__device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float u2, float q,
+                                                     const float* __restrict__ lds, float (&s)[kSums],
+                                                     float (&c)[kSums])
+{
+    float P[kSums];
+#pragma unroll
+    for (int j = 0; j < kSums; ++j)
+        P[j] = 0.f;
+    int sl = 0;
+    if (n >= 4) {
+        hodmas_chan_entry ea[4], eb[4];
+        load_group(E, ea);
+        int groups = 0;
+        while (true) {
+            const bool more_a = sl + 8 <= n;
+            process_group_all<KMAX, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
+            if (COMP && (++groups & 3) == 0)
+                flush_all<KMAX, COMP>(s, c, P);
+            sl += 4;
+            if (!more_a)
+                break;
+            const bool more_b = sl + 8 <= n;
+            process_group_all<KMAX, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
+            if (COMP && (++groups & 3) == 0)
+                flush_all<KMAX, COMP>(s, c, P);
+            sl += 4;
+            if (!more_b)
+                break;
+        }
+    }
+    for (; sl < n; ++sl) {
+        const hodmas_chan_entry e = E[sl];
+        const Tap tp = locate(e, u2, q);
+        float T[kSums];
+        terms_all<KMAX>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
+#pragma unroll
+        for (int j = 0; j < kSums; ++j) {
+            if (!sum_needed(j, KMAX))
+                continue;
+            if (COMP)
+                P[j] += T[j];
+            else
+                s[j] += T[j];
+        }
+    }
+    if (COMP)
+        flush_all<KMAX, COMP>(s, c, P);
+}
+
+template <int K, bool COMP>
+__device__ __forceinline__ void store_order(const float (&s)[kSums], const float (&c)[kSums], float out_scale,
+                                            float* __restrict__ dst)
+{
+    using R = typename std::conditional<(K >= 5), double, float>::type;
+    R p[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        p[j] = COMP ? R(s[kSumOf[K][j]]) - R(c[kSumOf[K][j]]) : R(s[kSumOf[K][j]]);
+    *dst = (float)(newton<K, R>(p) * R(out_scale));
+}
+
+template <int KMAX, int DT, bool COMP>
+__global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, OrderImages out)
+{
+    extern __shared__ float lds[];
+    constexpr int NT = kSums;
+    const hodmas_tile_desc td = ConstTile(A.tiles)[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int npix = A.block / A.split;
+    const int nwaves = A.block >> 6;
+    const int g = __builtin_amdgcn_readfirstlane(tid / npix);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int pl = tid - g * npix;
+    const int lx = pl % A.tile_x, lz = pl / A.tile_x;
+    const bool valid = lx < td.nx && lz < td.nz;
+    const int ix = td.ix0 + min(lx, td.nx - 1);
+    const int iz = td.iz0 + min(lz, td.nz - 1);
+    const int64_t pix = (int64_t)iz * A.nx + ix;
+
+    const double u = A.x0s + ix * A.dxs - td.xa;
+    const double w = A.z0s + iz * A.dzs - td.za;
+    const float u2 = (float)(2.0 * u);
+    const float q = (float)(u * u + w * (w + 2.0 * td.za));
+
+    float s[NT], c[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        // unneeded sums stay zero and are never read
+        s[j] = 0.f;
+        c[j] = 0.f;
+    }
+    ConstEntry E = ConstEntry(A.entries) + td.first_entry;
+    ConstStage St = ConstStage(A.stage) + td.first_entry;
+    for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
+        const int nch = min(A.chunk, td.n_active - c0);
+        __syncthreads();
+        stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        __syncthreads();
+        int goff = 0;
+        for (int h = 0; h < g; ++h)
+            goff += (nch - h + A.split - 1) / A.split;
+        const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
+        if (td.check)
+            accumulate_chunk_all<KMAX, COMP, true>(E + c0 + goff, ng, u2, q, lds, s, c);
+        else
+            accumulate_chunk_all<KMAX, COMP, false>(E + c0 + goff, ng, u2, q, lds, s, c);
+    }
+    if (A.split > 1) {
+        __syncthreads();
+        float* red = lds;
+        if (g > 0) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                if (!sum_needed(j, KMAX))
+                    continue;
+                red[((g - 1) * npix + pl) * 2 * NT + 2 * j] = s[j];
+                red[((g - 1) * npix + pl) * 2 * NT + 2 * j + 1] = c[j];
+            }
+        }
+        __syncthreads();
+        if (g == 0) {
+            for (int gg = 1; gg < A.split; ++gg) {
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    if (!sum_needed(j, KMAX))
+                        continue;
+                    const float so = red[((gg - 1) * npix + pl) * 2 * NT + 2 * j];
+                    const float co = red[((gg - 1) * npix + pl) * 2 * NT + 2 * j + 1];
+                    if (COMP) {
+                        kahan_add(s[j], c[j], so);
+                        kahan_add(s[j], c[j], -co);
+                    } else {
+                        s[j] += so;
+                    }
+                }
+            }
+        }
+    }
+    if (g != 0 || !valid)
+        return;
+    // orders with fewer contributing elements than k are exactly 0
+    const int na = td.n_active;
+    if (na >= 1) store_order<1, COMP>(s, c, A.out_scale, out.img[0] + pix); else out.img[0][pix] = 0.f;
+    if constexpr (KMAX >= 2) { if (na >= 2) store_order<2, COMP>(s, c, A.out_scale, out.img[1] + pix); else out.img[1][pix] = 0.f; }
+    if constexpr (KMAX >= 3) { if (na >= 3) store_order<3, COMP>(s, c, A.out_scale, out.img[2] + pix); else out.img[2][pix] = 0.f; }
+    if constexpr (KMAX >= 4) { if (na >= 4) store_order<4, COMP>(s, c, A.out_scale, out.img[3] + pix); else out.img[3][pix] = 0.f; }
+    if constexpr (KMAX >= 5) { if (na >= 5) store_order<5, COMP>(s, c, A.out_scale, out.img[4] + pix); else out.img[4][pix] = 0.f; }
+    if constexpr (KMAX >= 6) { if (na >= 6) store_order<6, COMP>(s, c, A.out_scale, out.img[5] + pix); else out.img[5][pix] = 0.f; }
+}
+
+template <int KMAX, int DT>
+int launch_orders_k(const FrameArgs& a, const OrderImages& out, bool comp, int64_t lds_bytes, hipStream_t st)
+{
+    dim3 grid(a.n_tiles), block(a.block);
+    if (comp)
+        hipLaunchKernelGGL((hodmas_orders_kernel<KMAX, DT, true>), grid, block, (size_t)lds_bytes, st, a, out);
+    else
+        hipLaunchKernelGGL((hodmas_orders_kernel<KMAX, DT, false>), grid, block, (size_t)lds_bytes, st, a, out);
+    return (int)hipGetLastError();
+}
+
+template <int DT>
+int launch_orders_dt(const FrameArgs& a, const OrderImages& out, int kmax, bool comp, int64_t lds_bytes,
+                     hipStream_t st)
+{
+    switch (kmax) {
+    case 1: return launch_orders_k<1, DT>(a, out, comp, lds_bytes, st);
+    case 2: return launch_orders_k<2, DT>(a, out, comp, lds_bytes, st);
+    case 3: return launch_orders_k<3, DT>(a, out, comp, lds_bytes, st);
+    case 4: return launch_orders_k<4, DT>(a, out, comp, lds_bytes, st);
+    case 5: return launch_orders_k<5, DT>(a, out, comp, lds_bytes, st);
+    case 6: return launch_orders_k<6, DT>(a, out, comp, lds_bytes, st);
+    }
+    return (int)hipErrorInvalidValue;
+}
+
 template <int K, int DT>
 int launch_k(const FrameArgs& a, bool comp, int64_t lds_bytes, hipStream_t st)
 {
-    dim3 grid(a.n_tiles), block(kBlock);
+    dim3 grid(a.n_tiles), block(a.block);
     if (comp)
         hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true>), grid, block, (size_t)lds_bytes, st, a);
     else
@@ -487,6 +801,18 @@ const void* batch_fn_dt(int order, bool comp)
     case 6: return batch_fn<6, DT>(comp);
     }
     return nullptr;
+}
+
+int launch_orders(const FrameArgs& a, const OrderImages& out, int kmax, int dtype, bool compensated,
+                  int64_t lds_bytes, void* stream)
+{
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    switch (dtype) {
+    case HODMAS_F32: return launch_orders_dt<HODMAS_F32>(a, out, kmax, compensated, lds_bytes, st);
+    case HODMAS_F16: return launch_orders_dt<HODMAS_F16>(a, out, kmax, compensated, lds_bytes, st);
+    case HODMAS_I16: return launch_orders_dt<HODMAS_I16>(a, out, kmax, compensated, lds_bytes, st);
+    }
+    return (int)hipErrorInvalidValue;
 }
 
 const void* batch_kernel(int order, int dtype, bool compensated)

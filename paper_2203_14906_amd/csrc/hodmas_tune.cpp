@@ -31,7 +31,8 @@ std::string tune_key(const char* arch, const hodmas_geometry* g, const hodmas_gr
                   "dt%d|S%d|st%lld|k%d|f%u",
                   arch, g->n_elements, g->pitch_m, g->sound_speed_m_s, g->fs_hz, g->t0_s, h, gr->nx,
                   gr->nz, gr->x0_m, gr->dx_m, gr->z0_m, gr->dz_m, rf->dtype, rf->n_samples,
-                  (long long)rf->channel_stride, order, (unsigned)(flags & HODMAS_FLAG_ACC_PLAIN));
+                  (long long)rf->channel_stride, order,
+                  (unsigned)(flags & (HODMAS_FLAG_ACC_PLAIN | HODMAS_FLAG_TUNE_BATCH)));
     return buf;
 }
 
@@ -89,8 +90,8 @@ extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const 
         return HODMAS_OK;
 
     static const hodmas_tiling kCandidates[] = {
-        {16, 16, 1, 64}, {16, 16, 1, 128}, {32, 8, 1, 64}, {8, 32, 1, 64},
-        {16, 8, 2, 64},  {16, 8, 2, 128},  {8, 8, 4, 64},  {8, 8, 4, 128},
+        {16, 16, 1, 64}, {16, 16, 1, 128}, {32, 8, 1, 64},  {8, 32, 1, 64},  {16, 8, 2, 64},
+        {8, 8, 4, 64},   {16, 16, 2, 64},  {32, 8, 2, 64},  {32, 16, 1, 64}, {16, 8, 4, 64},
     };
     const size_t esz = rf->dtype == HODMAS_F32 ? 4 : 2;
     const size_t rf_bytes = esz * (size_t)rf->channel_stride * (size_t)geometry->n_elements;
@@ -117,8 +118,11 @@ extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const 
     double best_us = 1e300;
     hodmas_tiling best{};
     for (const hodmas_tiling& cand : kCandidates) {
+        if ((flags & HODMAS_FLAG_TUNE_BATCH) && cand.tile_x * cand.tile_z * cand.split != hodmas::kBlock)
+            continue;   // members of a batch run 256-thread tiles
         hodmas_plan_t p = nullptr;
-        if (hodmas_plan(geometry, grid, rf, order, flags & ~HODMAS_FLAG_HOST_ONLY, &cand, &p) != HODMAS_OK)
+        if (hodmas_plan(geometry, grid, rf, order, flags & ~(HODMAS_FLAG_HOST_ONLY | HODMAS_FLAG_TUNE_BATCH),
+                        &cand, &p) != HODMAS_OK)
             continue;
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w)

@@ -20,6 +20,7 @@ MAX_ORDER = 6
 FLAG_ACC_PLAIN = 0x1
 FLAG_HOST_ONLY = 0x2
 FLAG_FORCE_CHECK = 0x4
+FLAG_TUNE_BATCH = 0x8
 
 _DTYPE_NAMES = {"f32": F32, "f16": F16, "i16": I16, "float32": F32, "float16": F16, "int16": I16}
 
@@ -94,6 +95,8 @@ def _load():
                               i32, u32, ctypes.POINTER(Tiling), ctypes.POINTER(vp)]
     L.hodmas_beamform.restype = i32
     L.hodmas_beamform.argtypes = [vp, vp, i32, vp, vp]
+    L.hodmas_beamform_orders.restype = i32
+    L.hodmas_beamform_orders.argtypes = [vp, vp, i32, ctypes.POINTER(vp), vp]
     L.hodmas_destroy.restype = i32
     L.hodmas_destroy.argtypes = [vp]
     L.hodmas_status_string.restype = ctypes.c_char_p
@@ -246,6 +249,24 @@ class Plan:
                                    ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
                "hodmas_beamform")
         return out
+
+    def beamform_orders(self, rf, max_order, outs=None, stream=None):
+        """Orders 1..max_order of ``rf`` in one pass; returns the list of images
+        (``outs[k-1]`` receives order k)."""
+        import torch
+        _check_tensor(rf, self)
+        if outs is None:
+            outs = [torch.empty((self.nz, self.nx), dtype=torch.float32, device=rf.device)
+                    for _ in range(max_order)]
+        if len(outs) < max_order:
+            raise ValueError("need one output image per order")
+        for o in outs[:max_order]:
+            if o.dtype != torch.float32 or not o.is_contiguous() or o.numel() != self.nx * self.nz or not o.is_cuda:
+                raise ValueError("each output must be a contiguous float32 GPU tensor of nz*nx elements")
+        ptrs = (ctypes.c_void_p * max_order)(*[o.data_ptr() for o in outs[:max_order]])
+        _check(lib.hodmas_beamform_orders(self._h, ctypes.c_void_p(rf.data_ptr()), int(max_order), ptrs,
+                                          _stream_handle(stream)), "hodmas_beamform_orders")
+        return outs[:max_order]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -4,8 +4,9 @@ Requests (a frame to beamform at some order) arrive over time.  Array geometry
 and the plans' delay tables stay resident on the device.  A request is admitted
 while the in-flight footprint (its RF and image bytes) fits an HBM budget; the
 admitted requests that are waiting when a launch slot frees up go out together
-as one persistent batched launch on that slot's stream, while earlier slots
-may still be running -- so work from different arrivals overlaps on the GPU.
+on that slot's stream -- as one batched submission, or as the frame's own
+kernel when only one is waiting -- while earlier slots may still be running,
+so work from different arrivals overlaps on the GPU.
 Completion is observed through HIP events; latency = completion - arrival.
 
 The plain comparison runs one synchronous float32 hodmas_beamform per request
@@ -33,6 +34,7 @@ class Request:
     done: float = -1.0        # completion time, seconds from the start
     image: object = None      # device tensor
     nbytes: int = 0
+    waited: bool = False      # held back at least once by the HBM budget
 
 
 @dataclass
@@ -54,7 +56,7 @@ class ServeStats:
     latencies_ms: np.ndarray = field(default_factory=lambda: np.zeros(0))
     launches: int = 0
     max_inflight: int = 0
-    admission_waits: int = 0
+    admission_waits: int = 0     # requests held back at least once by the budget
 
     def summary(self) -> dict:
         lat = self.latencies_ms
@@ -90,7 +92,6 @@ class FramePool:
                     rf32 = torch.from_numpy(ph.to_fp32(f.rf)).to(device) if plain else None
                     for side in sides:
                         self.frames.append(PoolFrame(n, S, side, rf16, rf32))
-        width = {}
         for fr in self.frames:
             key = (fr.n_elements, fr.n_samples, fr.side)
             if key not in self._plans:
@@ -180,7 +181,9 @@ class Server:
                 r = pending[0]
                 nb = self._footprint(r)
                 if inflight_bytes + nb > self.budget and (inflight_bytes > 0 or admitted):
-                    stats.admission_waits += 1
+                    if not r.waited:
+                        r.waited = True
+                        stats.admission_waits += 1
                     break
                 pending.popleft()
                 r.nbytes = nb
@@ -194,10 +197,15 @@ class Server:
                     if s["event"] is None:
                         take = [admitted.popleft() for _ in range(min(self.max_batch, len(admitted)))]
                         frs = [self.pool.frames[r.frame] for r in take]
-                        b = s["batch"]
-                        b.set([f.plan16 for f in frs], [f.rf16 for f in frs], [r.order for r in take],
-                              [r.image for r in take], stream=s["stream"])
-                        b.launch(stream=s["stream"])
+                        if len(take) == 1:
+                            # a lone request runs its frame's own kernel: no work list to build
+                            frs[0].plan16.beamform(frs[0].rf16, take[0].order, take[0].image,
+                                                   stream=s["stream"])
+                        else:
+                            b = s["batch"]
+                            b.set([f.plan16 for f in frs], [f.rf16 for f in frs], [r.order for r in take],
+                                  [r.image for r in take], stream=s["stream"])
+                            b.launch(stream=s["stream"])
                         ev = torch.cuda.Event()
                         ev.record(s["stream"])
                         s["event"], s["reqs"] = ev, take
@@ -206,14 +214,14 @@ class Server:
                         stats.max_inflight = max(stats.max_inflight, inflight_reqs)
                         break
             if finished < total:
+                # idle: sleep until shortly before the next arrival; with work in
+                # flight keep polling the completion events
                 nxt = pending[0].arrival if pending else None
                 busy = any(s["event"] is not None for s in self.slots)
                 if not busy and not admitted and nxt is not None:
                     delay = nxt - (time.perf_counter() - t0)
                     if delay > 2e-4:
                         time.sleep(delay - 1e-4)
-                else:
-                    time.sleep(2e-5)
         stats.wall_s = max(r.done for r in requests) if requests else 0.0
         stats.latencies_ms = np.array([(r.done - r.arrival) * 1e3 for r in requests])
         return stats

@@ -49,6 +49,8 @@ def test_argument_validation():
     assert _status(lambda: _plan(g, grid, 256, max_order=7)) == E
     assert _status(lambda: _plan(g, grid, 256, tiling=(16, 16, 3, 64))) == E
     assert _status(lambda: _plan(g, grid, 256, tiling=(16, 8, 1, 64))) == E
+    assert _status(lambda: _plan(g, grid, 256, tiling=(16, 16, 4, 64))) == E     # 1024 threads
+    _plan(g, grid, 256, tiling=(16, 16, 2, 64)).close()                         # 512 threads
     # delays beyond float32's exact-integer range are refused
     assert _status(lambda: _plan(g, ph.Grid(4, 4, 0.0, 1e-4, 1e4, 1e-4), 256)) == E
 
@@ -62,6 +64,9 @@ def test_null_pointers_and_destroy():
     p = _plan(ph.Geometry(8), ph.make_grid(8, 8, 2.4e-3, 3e-3), 128)
     # a host-only plan has no device tables to launch with
     assert L.hodmas_beamform(p.handle, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None) == hodmas.EINVAL
+    imgs = (ctypes.c_void_p * 6)(*([16] * 6))
+    assert L.hodmas_beamform_orders(None, ctypes.c_void_p(16), 2, imgs, None) == hodmas.EINVAL
+    assert L.hodmas_beamform_orders(p.handle, ctypes.c_void_p(16), 2, imgs, None) == hodmas.EINVAL
     assert L.hodmas_plan_get_info(p.handle, None) == hodmas.EINVAL
     p.close()
 
