@@ -111,7 +111,8 @@ typedef struct {
     int32_t tile_x;              /* pixels per tile along x */
     int32_t tile_z;              /* pixels per tile along z */
     int32_t split;               /* wave groups sharing one pixel's elements: 1, 2 or 4 */
-    int32_t chunk;               /* elements staged in LDS at a time */
+    int32_t chunk;               /* elements staged in LDS at a time; 0: as many as
+                                    fit 40 KB, so four workgroups share a CU */
 } hodmas_tiling;
 
 typedef struct hodmas_plan_s* hodmas_plan_t;

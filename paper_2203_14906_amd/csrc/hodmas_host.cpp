@@ -89,13 +89,13 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 hodmas_tiling default_tiling(const hodmas_grid& gr)
 {
     const int64_t want = 2 * 256;  // two workgroups per CU
-    hodmas_tiling t{16, 16, 1, 64};
+    hodmas_tiling t{16, 16, 1, 0};
     if (ceil_div(gr.nx, 16) * ceil_div(gr.nz, 16) >= want)
         return t;
-    t = {16, 8, 2, 64};
+    t = {16, 8, 2, 0};
     if (ceil_div(gr.nx, 16) * ceil_div(gr.nz, 8) >= want)
         return t;
-    return {8, 8, 4, 64};
+    return {8, 8, 4, 0};
 }
 
 void free_device(hodmas_plan_s* p)
@@ -298,8 +298,11 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
                            : (i - (geometry->n_elements - 1) / 2.0) * geometry->pitch_m;
     bool given = tiling && (tiling->tile_x || tiling->tile_z || tiling->split || tiling->chunk);
     p->tiling = given ? *tiling : default_tiling(*grid);
-    if (p->tiling.chunk == 0)
-        p->tiling.chunk = 64;
+    // chunk 0: every element at once for now; the windows (which do not depend
+    // on the chunk) then decide how many fit the LDS budget
+    const bool auto_chunk = p->tiling.chunk == 0;
+    if (auto_chunk)
+        p->tiling.chunk = std::max(1, geometry->n_elements);
     st = build_tables(p);
     if (st != HODMAS_OK) {
         delete p;
@@ -309,7 +312,8 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     const int64_t block = int64_t(p->tiling.tile_x) * p->tiling.tile_z * p->tiling.split;
     const int64_t reduce_bytes = int64_t(block / p->tiling.split) * (p->tiling.split - 1) *
                                  HODMAS_MAX_ORDER * 2 * 4;
-    const int64_t cap = 64 * 1024;
+    // 40 KB keeps four workgroups on a CU (160 KB); an explicit chunk may use 64 KB
+    const int64_t cap = auto_chunk ? 40 * 1024 : 64 * 1024;
     if (int64_t(p->max_window) * 4 > hodmas::kMaxLdsBytes) {
         delete p;
         return HODMAS_EUNSUPPORTED;

@@ -43,6 +43,8 @@ struct OrderImages {
 constexpr int kBatchKinds = HODMAS_MAX_ORDER * 3;
 constexpr int batch_kind(int order, int dtype) { return (order - 1) * 3 + dtype; }
 
+constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
+
 struct BatchHeader {
     int32_t n_units;
     int32_t n_frames;

@@ -31,6 +31,38 @@ using ConstTile = const hodmas_tile_desc* __restrict__;
 using ConstEntry = const hodmas_chan_entry* __restrict__;
 using ConstStage = const hodmas_stage_entry* __restrict__;
 
+// The tables and work lists are never written by a kernel.  Their elements
+// are read through the constant address space, which says so: loads at
+// wave-uniform addresses then become scalar loads even after the kernel has
+// stored to global memory (the batch kernels store a tile's pixels before
+// reading the next tile's entries), and pointers that were themselves read
+// from memory are not left as flat pointers.  The copy goes dword by dword
+// (every table record is a whole number of dwords).
+template <class T>
+__device__ __forceinline__ T load_const(const T* base, int64_t index)
+{
+    static_assert(sizeof(T) % 4 == 0, "table records are whole dwords");
+    using CP = const __attribute__((address_space(4))) int*;
+    const CP p = (CP)(const void*)(base + index);
+    T out;
+    int* o = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int i = 0; i < int(sizeof(T) / 4); ++i)
+        o[i] = p[i];
+    return out;
+}
+
+// RF records and images live in global memory; saying so keeps accesses
+// through pointers read from a work list global rather than flat (flat loads
+// also count against the LDS wait counter).
+template <class T>
+using Global = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ Global<T> global_ptr(T* p)
+{
+    return (Global<T>)p;
+}
+
 template <int DT> struct Storage;
 template <> struct Storage<HODMAS_F32> { using T = float; };
 template <> struct Storage<HODMAS_F16> { using T = _Float16; };
@@ -130,36 +162,50 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
                                             float* __restrict__ lds, int wave, int nwaves, int lane)
 {
     using T = typename Storage<DT>::T;
-    const T* __restrict__ rf = static_cast<const T*>(A.rf);
+    const Global<const T> rf = global_ptr(static_cast<const T*>(A.rf));
+    constexpr int kInFlight = 16;      // loads issued per lane before the first wait
     for (int base = 0; base < window; base += 64) {
         const int i = base + lane;
-        int c = wave;
-        // four elements per pass so four loads are in flight per lane
-        for (; c + 3 * nwaves < nch; c += 4 * nwaves) {
-            float v[4];
+        for (int c = wave; c < nch; c += kInFlight * nwaves) {
+            // every load is issued unconditionally from a clamped, in-bounds
+            // address (the element index to the chunk, the sample to the
+            // record), so they are in flight together instead of one round
+            // trip each; out-of-range lanes then store zero.  The table
+            // entries come first ...
+            hodmas_stage_entry se[kInFlight];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const hodmas_stage_entry se = st[c + m * nwaves];
-                const int t = se.first_sample + i;
-                v[m] = 0.f;
-                if (i < window && t >= 0 && t < A.n_samples)
-                    v[m] = widen(rf[(int64_t)se.channel * A.stride + t]) * A.in_scale;
+            for (int m = 0; m < kInFlight; ++m)
+                se[m] = load_const(st, __builtin_amdgcn_readfirstlane(min(c + m * nwaves, nch - 1)));
+            __builtin_amdgcn_sched_barrier(0);
+            // ... then the samples they point at
+            float v[kInFlight];
+#pragma unroll
+            for (int m = 0; m < kInFlight; ++m) {
+                const int cm = c + m * nwaves;
+                const int t = se[m].first_sample + i;
+                const int tc = min(max(t, 0), A.n_samples - 1);
+                const float x = widen(rf[(int64_t)se[m].channel * A.stride + tc]) * A.in_scale;
+                v[m] = (cm < nch && i < window && t == tc) ? x : 0.f;
             }
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
-                if (i < window)
-                    lds[(c + m * nwaves) * window + i] = v[m];
-        }
-        for (; c < nch; c += nwaves) {
-            const hodmas_stage_entry se = st[c];
-            const int t = se.first_sample + i;
-            float v = 0.f;
-            if (i < window && t >= 0 && t < A.n_samples)
-                v = widen(rf[(int64_t)se.channel * A.stride + t]) * A.in_scale;
-            if (i < window)
-                lds[c * window + i] = v;
+            for (int m = 0; m < kInFlight; ++m) {
+                const int cm = c + m * nwaves;
+                if (cm < nch && i < window)
+                    lds[cm * window + i] = v[m];
+            }
         }
     }
+}
+
+// Workgroups are dealt to the eight XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  Give each XCD a contiguous run of tiles -- a band of tile rows --
+// so the RF samples an XCD stages come from a narrow range of delays and its
+// own L2 holds them, instead of every XCD fetching the whole frame.
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n / kXcds, r = n % kXcds;
+    const int x = b % kXcds, l = b / kXcds;
+    return x * q + min(x, r) + l;
 }
 
 // Power-sum accumulation.  Compensated mode: four elements are summed pairwise,
@@ -180,7 +226,7 @@ __device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[
 {
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        e[m] = E[m];
+        e[m] = load_const(E, m);
 }
 
 // One group of four elements: delays and LDS addresses, the four gathers
@@ -267,7 +313,7 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         }
     }
     for (; sl < n; ++sl) {
-        const hodmas_chan_entry e = E[sl];
+        const hodmas_chan_entry e = load_const(E, sl);
         const Tap tp = locate(e, u2, q);
         float T[K];
         powers<K>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
@@ -308,7 +354,7 @@ __device__ __forceinline__ R newton(const R (&p)[K])
 template <int K, int DT, bool COMP>
 __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
 {
-    const hodmas_tile_desc td = ConstTile(A.tiles)[tile];
+    const hodmas_tile_desc td = load_const(A.tiles, tile);
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
     const int nwaves = A.block >> 6;
@@ -320,7 +366,7 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     const bool valid = lx < td.nx && lz < td.nz;
     const int ix = td.ix0 + min(lx, td.nx - 1);
     const int iz = td.iz0 + min(lz, td.nz - 1);
-    float* __restrict__ dst = A.image + (int64_t)iz * A.nx + ix;
+    const Global<float> dst = global_ptr(A.image + (int64_t)iz * A.nx + ix);
 
     if (td.n_active < K) {
         // fewer contributing elements than the order: no K-subset exists, e_K = 0 exactly
@@ -341,8 +387,8 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
         s[j] = 0.f;
         c[j] = 0.f;
     }
-    ConstEntry E = ConstEntry(A.entries) + td.first_entry;
-    ConstStage St = ConstStage(A.stage) + td.first_entry;
+    ConstEntry E = A.entries + td.first_entry;
+    ConstStage St = A.stage + td.first_entry;
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();                       // previous readers of the LDS are done
@@ -402,7 +448,7 @@ template <int K, int DT, bool COMP>
 __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 {
     extern __shared__ float lds[];
-    process_tile<K, DT, COMP>(A, blockIdx.x, lds);
+    process_tile<K, DT, COMP>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
 }
 
 // Persistent form: one kernel per (order, storage type).  Its fixed grid walks
@@ -412,21 +458,23 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 // cost).  Each tile runs exactly the code of the per-frame kernel, so a frame's
 // image does not depend on what else is in the batch.
 template <int K, int DT, bool COMP>
-__global__ __launch_bounds__(kBlock) void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr,
+__global__ __launch_bounds__(kMaxBlock) void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                               const BatchFrame* __restrict__ frames,
                                                               const BatchUnit* __restrict__ units)
 {
     extern __shared__ float lds[];
     constexpr int kind = batch_kind(K, DT);
-    const int first = hdr->begin[kind];
-    const int n = hdr->end[kind] - first;
+    const BatchHeader h = load_const(hdr, 0);
+    const int first = h.begin[kind];
+    const int n = h.end[kind] - first;
     const int G = gridDim.x;
     for (int r = 0; r * G < n; ++r) {
         const int u = (r & 1) ? (r + 1) * G - 1 - (int)blockIdx.x : r * G + (int)blockIdx.x;
         if (u >= n)
             continue;
-        const BatchUnit un = units[first + u];
-        process_tile<K, DT, COMP>(frames[un.frame].args, un.tile, lds);
+        const BatchUnit un = load_const(units, first + u);
+        const BatchFrame fr = load_const(frames, un.frame);
+        process_tile<K, DT, COMP>(fr.args, un.tile, lds);
     }
 }
 
@@ -597,7 +645,7 @@ __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float 
         }
     }
     for (; sl < n; ++sl) {
-        const hodmas_chan_entry e = E[sl];
+        const hodmas_chan_entry e = load_const(E, sl);
         const Tap tp = locate(e, u2, q);
         float T[kSums];
         terms_all<KMAX>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
@@ -632,7 +680,7 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
 {
     extern __shared__ float lds[];
     constexpr int NT = kSums;
-    const hodmas_tile_desc td = ConstTile(A.tiles)[blockIdx.x];
+    const hodmas_tile_desc td = load_const(A.tiles, xcd_tile(blockIdx.x, A.n_tiles));
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
     const int nwaves = A.block >> 6;
@@ -658,8 +706,8 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
         s[j] = 0.f;
         c[j] = 0.f;
     }
-    ConstEntry E = ConstEntry(A.entries) + td.first_entry;
-    ConstStage St = ConstStage(A.stage) + td.first_entry;
+    ConstEntry E = A.entries + td.first_entry;
+    ConstStage St = A.stage + td.first_entry;
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();
