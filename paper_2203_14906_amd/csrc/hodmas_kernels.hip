@@ -163,35 +163,38 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
 {
     using T = typename Storage<DT>::T;
     const Global<const T> rf = global_ptr(static_cast<const T*>(A.rf));
-    constexpr int kInFlight = 16;      // loads issued per lane before the first wait
-    for (int base = 0; base < window; base += 64) {
-        const int i = base + lane;
-        for (int c = wave; c < nch; c += kInFlight * nwaves) {
-            // every load is issued unconditionally from a clamped, in-bounds
-            // address (the element index to the chunk, the sample to the
-            // record), so they are in flight together instead of one round
-            // trip each; out-of-range lanes then store zero.  The table
-            // entries come first ...
-            hodmas_stage_entry se[kInFlight];
+    // Each wave stages a contiguous run of slots; lanes run along the window.
+    // Latency, not bandwidth, sets the cost here: one vector load brings 64
+    // slots' table entries (lane j holds slot j), then the sample loads go out
+    // kInFlight at a time before any wait, their addresses read out of the
+    // entry lanes.  Every load address is clamped in bounds (slot to the
+    // chunk, sample to the record); out-of-range lanes store zero.
+    constexpr int kInFlight = 16;
+    const int per_wave = (nch + nwaves - 1) / nwaves;
+    const int s0 = wave * per_wave;
+    const int s1 = min(nch, s0 + per_wave);
+    const Global<const int> ent = global_ptr(reinterpret_cast<const int*>(st));
+    for (int c = s0; c < s1; c += 64) {
+        const int j = min(c + lane, s1 - 1);
+        const int my_channel = ent[2 * j];
+        const int my_first = ent[2 * j + 1];
+        const int cend = min(s1 - c, 64);
+        for (int base = 0; base < window; base += 64) {
+            const int i = base + lane;
+            for (int m0 = 0; m0 < cend; m0 += kInFlight) {
+                float v[kInFlight];
 #pragma unroll
-            for (int m = 0; m < kInFlight; ++m)
-                se[m] = load_const(st, __builtin_amdgcn_readfirstlane(min(c + m * nwaves, nch - 1)));
-            __builtin_amdgcn_sched_barrier(0);
-            // ... then the samples they point at
-            float v[kInFlight];
+                for (int m = 0; m < kInFlight; ++m) {
+                    const int ch = __builtin_amdgcn_readlane(my_channel, m0 + m);
+                    const int t = __builtin_amdgcn_readlane(my_first, m0 + m) + i;
+                    const int tc = min(max(t, 0), A.n_samples - 1);
+                    const float x = widen(rf[(int64_t)ch * A.stride + tc]) * A.in_scale;
+                    v[m] = (m0 + m < cend && i < window && t == tc) ? x : 0.f;
+                }
 #pragma unroll
-            for (int m = 0; m < kInFlight; ++m) {
-                const int cm = c + m * nwaves;
-                const int t = se[m].first_sample + i;
-                const int tc = min(max(t, 0), A.n_samples - 1);
-                const float x = widen(rf[(int64_t)se[m].channel * A.stride + tc]) * A.in_scale;
-                v[m] = (cm < nch && i < window && t == tc) ? x : 0.f;
-            }
-#pragma unroll
-            for (int m = 0; m < kInFlight; ++m) {
-                const int cm = c + m * nwaves;
-                if (cm < nch && i < window)
-                    lds[cm * window + i] = v[m];
+                for (int m = 0; m < kInFlight; ++m)
+                    if (m0 + m < cend && i < window)
+                        lds[(c + m0 + m) * window + i] = v[m];
             }
         }
     }
