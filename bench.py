@@ -70,6 +70,25 @@ def main():
      "serve": bench_serve}[args.workload](args, torch)
 
 
+def _profiled_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or
+    None when no summary covers it or the kernel source changed since."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2203_14906_amd", "csrc", "hodmas_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        text = open(path).read()
+        if "kernel_source_sha256: " + sha not in text:
+            continue
+        for line in text.splitlines():
+            line = line.strip()
+            if line.startswith("traffic_bytes_per_launch " + kernel + ":"):
+                return int(line.rsplit(":", 1)[1])
+    return None
+
+
 def _events(torch, n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
@@ -128,6 +147,7 @@ def bench_plain(args, torch):
     value = total_pixch / elapsed / 1e9
     dom = max(orders, key=lambda k: per_order_ms[k])
     achieved = SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
+    dom_kernel = "hodmas_frame_kernel<%d, f32, %s>" % (dom, "comp")
 
     # every order 1..kmax from one launch per frame
     fused = None
@@ -148,11 +168,12 @@ def bench_plain(args, torch):
         torch.cuda.synchronize()
         f_ms = sum(a.elapsed_time(z) for a, z in fev) / (args.steps * args.batch)
         f_ach = FUSED_SLOTS[kmax] * pixch / (f_ms * 1e-3) / 1e12
-        fused = {"kernel": "hodmas_orders_kernel<%d, f32>" % kmax, "kernel_us_per_frame": round(f_ms * 1e3, 2),
+        fused = {"kernel": "hodmas_orders_kernel<%d, f32, comp>" % kmax, "kernel_us_per_frame": round(f_ms * 1e3, 2),
                  "gpixch_s_sum_orders": round(pixch * len(orders) / (f_ms * 1e-3) / 1e9, 2),
                  "speedup_vs_per_order_launches": round(sum(per_order_ms.values()) / f_ms, 3),
                  "slots_per_pixch": FUSED_SLOTS[kmax], "achieved_tslot_s": round(f_ach, 2),
-                 "frac": round(f_ach / VALU_PEAK_TSLOT, 4)}
+                 "frac": round(f_ach / VALU_PEAK_TSLOT, 4),
+                 "traffic": _profiled_traffic("hodmas_orders_kernel<%d, f32, comp>" % kmax)}
 
     # relative L2 of the last images against the oracle is checked by the tests;
     # here only the CPU oracle's throughput on the same batch is measured.
@@ -194,10 +215,11 @@ def bench_plain(args, torch):
         "per_order_gpixch_s": per_order,
         "per_order_kernel_us": {str(k): round(per_order_ms[k] * 1e3, 2) for k in orders},
         "fused_all_orders": fused,
-        "roofline": {"bound": "alu", "kernel": "hodmas_frame_kernel<%d, f32>" % dom,
+        "roofline": {"bound": "alu", "kernel": dom_kernel,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),
-                     "slots_per_pixch": SLOTS[dom], "traffic": None},
+                     "slots_per_pixch": SLOTS[dom], "traffic": _profiled_traffic(dom_kernel),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"},
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }
