@@ -106,6 +106,48 @@ def test_graph_replays_and_reset_work_list(hd):
         p.close()
 
 
+@pytest.mark.parametrize("comp", [True, False])
+def test_batch_multi_chunk_split_and_batch_lds(hd, comp):
+    # units of several chunks, split tilings (combined through LDS between
+    # units) and orders above the element count, one after another in a
+    # persistent workgroup
+    flags = 0 if comp else hd.FLAG_ACC_PLAIN
+    cases = [  # (N, S, nx, nz, order, dtype, tiling, extra flags)
+        (32, 512, 40, 36, 3, "f32", (16, 16, 1, 5), 0), (24, 400, 33, 29, 6, "f16", (8, 8, 4, 7), 0),
+        (48, 700, 45, 50, 2, "i16", (16, 8, 2, 9), 0), (128, 2048, 96, 96, 5, "f32", (8, 8, 4, 43), 0),
+        (256, 2048, 64, 64, 4, "f16", (8, 8, 4, 19), 0), (20, 300, 16, 16, 6, "f32", (16, 16, 1, 3), 0),
+        (64, 1024, 48, 48, 1, "i16", (16, 16, 1, 64), 0), (5, 200, 18, 18, 6, "f16", (8, 8, 4, 2), 0),
+    ]
+    plans, rfs, outs, orders = [], [], [], []
+    for i, (n, S, nx, nz, k, dt, til, fl) in enumerate(cases):
+        f = ph.make_frame(n, S, nx, nz, n_points=4, n_lines=1, snr_db=15.0, seed=900 + i)
+        if dt == "f32":
+            arr, scale = ph.to_fp32(f.rf), 1.0
+        elif dt == "f16":
+            arr, scale = ph.to_fp16(f.rf), 1.0
+        else:
+            arr, scale = ph.to_int16(f.rf, 900 + i)
+        p = hd.Plan(f.geometry, f.grid, S, dt, max_order=6, dequant_scale=float(scale), tiling=til,
+                    flags=flags | fl)
+        t = p.info().tiling
+        say("case %d: N=%d %dx%d k=%d %s tiling %s" % (i, n, nx, nz, k, dt, (t.tile_x, t.tile_z, t.split, t.chunk)))
+        plans.append(p)
+        rfs.append(torch.from_numpy(arr).cuda())
+        outs.append(torch.full((nz, nx), float("nan"), dtype=torch.float32, device="cuda"))
+        orders.append(k)
+    alone = [p.beamform(r, k).clone() for p, r, k in zip(plans, rfs, orders)]
+    lds = max(p.info().lds_bytes for p in plans)
+    batch = hd.Batch(max_frames=16, max_units=100000, max_lds_bytes=lds, flags=flags)
+    batch.set(plans, rfs, orders, outs)
+    batch.launch()
+    torch.cuda.synchronize()
+    for i, (a, b) in enumerate(zip(alone, outs)):
+        assert torch.equal(a, b), "case %d differs between the batch and its own launch" % i
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_rejects_bad_work_lists(hd):
     f = ph.make_frame(16, 256, 20, 20, n_points=2, seed=3)
     p4 = hd.Plan(f.geometry, f.grid, 256, "f32", max_order=4)
