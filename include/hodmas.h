@@ -276,6 +276,52 @@ hodmas_status hodmas_batch_destroy(hodmas_batch_t batch);
 /* Version string of the library. */
 const char* hodmas_version(void);
 
+/* -------------------------------------------------------------------------
+ * Display chain (Sec. III): the paper band-passes the beamformed image,
+ * detects its envelope with the Hilbert transform and log-compresses it for
+ * display.  Readings (the paper gives no values): a centred FIR along depth,
+ * the difference of two Hamming-windowed ideal low-pass responses with unit
+ * gain at the centre of the pass band, sampled at c/dz (one-way flight);
+ * samples beyond the image are zero.  The envelope is |analytic signal| of
+ * each depth column from its length-nz DFT (bin 0 and the Nyquist bin kept,
+ * bins 1..nz/2-1 doubled, the rest dropped).  The dB image is
+ * 20 log10(envelope / max envelope), clipped below at -dynamic_range_db (an
+ * all-zero image gives -dynamic_range_db everywhere).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t nx, nz;              /* image [nz][nx]; nz a power of two in 2..8192 */
+    double dz_m;                 /* depth step, > 0 */
+    double sound_speed_m_s;      /* > 0 */
+    double f_lo_hz, f_hi_hz;     /* pass band: 0 < f_lo < f_hi < c / (2 dz) */
+    int32_t numtaps;             /* odd, 1..255 */
+    float dynamic_range_db;      /* > 0 */
+} hodmas_display_desc;
+
+typedef struct hodmas_display_s* hodmas_display_t;
+
+/* The band-pass taps (numtaps doubles, caller-owned) for a description, on
+ * the host.  Errors: EINVAL (null pointers, even or out-of-range numtaps, a
+ * pass band outside (0, c/(2 dz)), non-positive dz or c). */
+hodmas_status hodmas_display_taps(const hodmas_display_desc* desc, double* taps);
+
+/* Validate the description and upload the taps and FFT twiddles to the
+ * current HIP device.  *out owns them until hodmas_display_destroy.
+ * Errors: EINVAL (as for hodmas_display_taps, nx < 1 or > 65536, nz not a
+ * power of two in range, dynamic range <= 0), ENOMEM. */
+hodmas_status hodmas_display_plan(const hodmas_display_desc* desc, hodmas_display_t* out);
+
+/* image_dev: device float32 [nz][nx] (e.g. a hodmas_beamform output).
+ * envelope_dev: device float32 [nz][nx] for the envelope, or NULL.
+ * db_dev: device float32 [nz][nx] for the dB image (may equal envelope_dev,
+ * must differ from image_dev).  Two asynchronous launches on `stream`; no
+ * allocation.  Errors: EINVAL (null image or dB pointer, aliasing the
+ * input), EDEVICE. */
+hodmas_status hodmas_display_run(hodmas_display_t display, const float* image_dev, float* envelope_dev,
+                                 float* db_dev, void* stream);
+
+/* Release a display plan.  NULL is accepted. */
+hodmas_status hodmas_display_destroy(hodmas_display_t display);
+
 #ifdef __cplusplus
 }
 #endif

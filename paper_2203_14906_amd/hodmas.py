@@ -84,10 +84,26 @@ class StageEntry(ctypes.Structure):
     _fields_ = [("channel", ctypes.c_int32), ("first_sample", ctypes.c_int32)]
 
 
+class DisplayDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("dz_m", ctypes.c_double),
+                ("sound_speed_m_s", ctypes.c_double), ("f_lo_hz", ctypes.c_double),
+                ("f_hi_hz", ctypes.c_double), ("numtaps", ctypes.c_int32),
+                ("dynamic_range_db", ctypes.c_float)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libhodmas.so is not built (run __graft_entry__.build() or "
                           "python paper_2203_14906_amd/build.py)")
+    # One process must hold one HIP runtime.  PyTorch ships its own
+    # libamdhip64; loading it first makes libhodmas.so bind to that copy, so
+    # tensors from torch and pointers handed to the library belong to the same
+    # runtime (loading the library first maps the system runtime beside
+    # torch's, and device copies then fail).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
     L.hodmas_plan.restype = i32
@@ -128,6 +144,14 @@ def _load():
                                   i32, u32, ctypes.c_char_p, ctypes.POINTER(Tiling)]
     L.hodmas_version.restype = ctypes.c_char_p
     L.hodmas_version.argtypes = []
+    L.hodmas_display_taps.restype = i32
+    L.hodmas_display_taps.argtypes = [ctypes.POINTER(DisplayDesc), ctypes.POINTER(ctypes.c_double)]
+    L.hodmas_display_plan.restype = i32
+    L.hodmas_display_plan.argtypes = [ctypes.POINTER(DisplayDesc), ctypes.POINTER(vp)]
+    L.hodmas_display_run.restype = i32
+    L.hodmas_display_run.argtypes = [vp, vp, vp, vp, vp]
+    L.hodmas_display_destroy.restype = i32
+    L.hodmas_display_destroy.argtypes = [vp]
     return L
 
 
@@ -346,3 +370,57 @@ def _check_tensor(rf, plan):
             rf.stride(0) != plan.channel_stride or rf.shape[1] < plan.n_samples:
         raise ValueError("rf must be [n_elements][>= n_samples] with row stride %d" % plan.channel_stride)
     return torch
+
+
+def _display_desc(nx, nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps, dynamic_range_db):
+    return DisplayDesc(int(nx), int(nz), float(dz_m), float(sound_speed_m_s), float(f_lo_hz), float(f_hi_hz),
+                       int(numtaps), float(dynamic_range_db))
+
+
+def display_taps(nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps, nx=1, dynamic_range_db=60.0):
+    """The band-pass taps the display chain uses (host computation)."""
+    d = _display_desc(nx, nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps, dynamic_range_db)
+    out = (ctypes.c_double * max(1, int(numtaps)))()
+    _check(lib.hodmas_display_taps(ctypes.byref(d), out), "hodmas_display_taps")
+    return [out[i] for i in range(int(numtaps))]
+
+
+class Display:
+    """Display chain of beamformed images [nz][nx]: band-pass along depth,
+    Hilbert envelope, log compression (see hodmas_display_run)."""
+
+    def __init__(self, nx, nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps=63, dynamic_range_db=60.0):
+        self.nx, self.nz = int(nx), int(nz)
+        d = _display_desc(nx, nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps, dynamic_range_db)
+        self._h = ctypes.c_void_p()
+        _check(lib.hodmas_display_plan(ctypes.byref(d), ctypes.byref(self._h)), "hodmas_display_plan")
+
+    def run(self, image, envelope=None, db=None, stream=None):
+        """Returns (envelope or None, dB image); allocates outputs not given."""
+        import torch
+        for t in (image, envelope, db):
+            if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                                  or tuple(t.shape) != (self.nz, self.nx)):
+                raise ValueError("images must be contiguous float32 GPU tensors [nz][nx]")
+        if db is None:
+            db = torch.empty_like(image)
+        _check(lib.hodmas_display_run(self._h, ctypes.c_void_p(image.data_ptr()),
+                                      ctypes.c_void_p(envelope.data_ptr()) if envelope is not None else None,
+                                      ctypes.c_void_p(db.data_ptr()), _stream_handle(stream)),
+               "hodmas_display_run")
+        return envelope, db
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.hodmas_display_destroy(self._h)
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
