@@ -40,10 +40,11 @@ FUSED_SLOTS = {1: 19, 2: 26, 3: 38, 4: 47, 5: 59, 6: 68}
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="plain", choices=["plain", "reduced", "batch", "serve"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "reduced", "batch", "serve", "display"],
                     help="plain: 128 el / 512^2 / FP32 (default); reduced: 256 el / 1024^2 / int16+FP16; "
                          "batch: 256 mixed FP16 frames in one persistent launch vs 256 FP32 launches; "
-                         "serve: Poisson arrivals, continuous batching vs plain FP32 per request")
+                         "serve: Poisson arrivals, continuous batching vs plain FP32 per request; "
+                         "display: band-pass + Hilbert envelope + log compression of beamformed images")
     ap.add_argument("--rates", default="500,1000,2000", help="serve: arrival rates (frames/s)")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: seconds per rate")
     ap.add_argument("--budget-gb", type=float, default=32.0, help="serve: HBM admission budget")
@@ -67,7 +68,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     {"plain": bench_plain, "reduced": bench_reduced, "batch": bench_batch,
-     "serve": bench_serve}[args.workload](args, torch)
+     "serve": bench_serve, "display": bench_display}[args.workload](args, torch)
 
 
 def _profiled_traffic(kernel):
@@ -396,6 +397,72 @@ def bench_serve(args, torch):
     srv.close()
     pool.close()
     print(json.dumps(out))
+
+
+
+
+def bench_display(args, torch):
+    """Display chain (band-pass 2-8 MHz, 63 taps, Hilbert envelope, 60 dB log
+    compression) of B beamformed 512x512 images (128 elements, order 3): image
+    throughput, the envelope kernel's HBM rate, and the FP64 oracle beside it."""
+    import numpy as np
+    from paper_2203_14906_amd import hodmas, phantom as ph
+    p = ph.CONFIGS[2]
+    frames = [ph.make_frame(p["n_elements"], p["n_samples"], p["nx"], p["nz"], n_points=p["n_points"],
+                            n_lines=p["n_lines"], snr_db=p["snr_db"], seed=2000 + b) for b in range(args.batch)]
+    grid = frames[0].grid
+    plan = hodmas.Plan(frames[0].geometry, grid, p["n_samples"], "f32", max_order=3)
+    images = [plan.beamform(torch.from_numpy(ph.to_fp32(f.rf)).cuda(), 3) for f in frames]
+    disp = hodmas.Display(grid.nx, grid.nz, grid.dz_m, 1540.0, 2e6, 8e6, 63, 60.0)
+    envs = [torch.empty_like(im) for im in images]
+    dbs = [torch.empty_like(im) for im in images]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for im, e, d in zip(images, envs, dbs):
+            disp.run(im, e, d, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = _events(torch, args.steps)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        step()
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = sum(a.elapsed_time(b) for a, b in ev) / (args.steps * args.batch)
+    npx = grid.nx * grid.nz
+    # algorithmic bytes per image: read the image, write envelope and dB image
+    algo_bytes = 3 * 4 * npx
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import display as D
+        t_cpu, n = time.perf_counter(), 0
+        for im in images:
+            D.display(im.cpu().numpy().astype(np.float64), grid.dz_m, 1540.0, 2e6, 8e6, 63, 60.0)
+            n += 1
+            if time.perf_counter() - t_cpu > 20.0:
+                break
+        dt = time.perf_counter() - t_cpu
+        cpu = {"value": round(n * npx / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+               "sample": "%d image(s) of the same batch, numpy FP64, %.1f s" % (n, dt)}
+    res = {"metric": "display chain Mpixel/s (band-pass, Hilbert envelope, log compression)",
+           "value": round(npx / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+           "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "display chain of %d beamformed 512x512 images (128 elements, order 3), "
+                                  "2-8 MHz band-pass with 63 taps, 60 dB" % args.batch},
+           "us_per_image": round(ms * 1e3, 2),
+           "roofline": {"bound": "hbm", "achieved": round(algo_bytes / (ms * 1e-3) / 1e9, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(algo_bytes / (ms * 1e-3) / 1e9 / 8000.0, 4),
+                        "traffic": None},
+           "cpu_baseline": cpu}
+    print(json.dumps(res))
+    disp.close()
+    plan.close()
 
 
 if __name__ == "__main__":

@@ -239,7 +239,16 @@ hodmas_status hodmas_display_plan(const hodmas_display_desc* d, hodmas_display_t
     p->desc = *d;
     while ((1 << p->log2n) < d->nz)
         ++p->log2n;
-    p->cols = std::max(1, std::min(16, kDispColsBudget / d->nz));
+    // columns per workgroup: as many as the LDS budget allows, but few enough
+    // that the grid still gives every CU two workgroups
+    int cus = 256;
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+    }
+    p->cols = std::max(1, std::min({16, kDispColsBudget / d->nz, d->nx / (2 * cus)}));
     p->n_blocks = (d->nx + p->cols - 1) / p->cols;
     std::vector<float> ft(d->numtaps);
     for (int k = 0; k < d->numtaps; ++k)
