@@ -102,17 +102,36 @@ double hodmas_oracle_esym(const double *y, int n, int order)
     return r;
 }
 
-/* One pixel: delays, interpolated samples, signed roots, symmetric sum. */
+/* Coherence factor of the n delayed samples v_i (the weighting the paper
+ * proposes to combine with its beamformers, Sec. VI; the factor itself is the
+ * standard one of the weighting literature it cites in Sec. I):
+ *   CF = (sum_i v_i)^2 / (n * sum_i v_i^2),
+ * with n the number of array elements (samples outside the record count as
+ * zeros); 0 when every sample is 0.  By Cauchy-Schwarz 0 <= CF <= 1. */
+double hodmas_oracle_coherence(const double *v, int n)
+{
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        s1 += v[i];
+        s2 += v[i] * v[i];
+    }
+    return s2 > 0.0 ? (s1 * s1) / ((double)n * s2) : 0.0;
+}
+
+/* One pixel: delays, interpolated samples, signed roots, symmetric sum;
+ * weighting 1 multiplies the sum by the coherence factor of the samples.
+ * y and v are caller scratch of n_el doubles each. */
 static double beamform_pixel(int n_el, const double *elem_x, double c, double fs, double t0,
                              int64_t n_samples, const double *rf, int64_t stride,
-                             double xp, double zp, int order, double *y)
+                             double xp, double zp, int order, int weighting, double *y, double *v)
 {
     for (int i = 0; i < n_el; ++i) {
         double t = hodmas_oracle_tof(elem_x[i], xp, zp, c, fs, t0);
-        double v = hodmas_oracle_sample(rf + (int64_t)i * stride, n_samples, t);
-        y[i] = hodmas_oracle_signed_root(v, order);
+        v[i] = hodmas_oracle_sample(rf + (int64_t)i * stride, n_samples, t);
+        y[i] = hodmas_oracle_signed_root(v[i], order);
     }
-    return hodmas_oracle_esym(y, n_el, order);
+    double e = hodmas_oracle_esym(y, n_el, order);
+    return weighting == 1 ? e * hodmas_oracle_coherence(v, n_el) : e;
 }
 
 static int check_args(int n_el, const double *elem_x, double c, double fs, int64_t n_samples,
@@ -126,19 +145,21 @@ static int check_args(int n_el, const double *elem_x, double c, double fs, int64
 }
 
 /* Whole image, row-major [nz][nx]; pixel (ix, iz) sits at
- * (x0 + ix*dx, z0 + iz*dz).  Returns 0 on success, 1 on bad arguments. */
-int hodmas_oracle_beamform(int n_el, const double *elem_x, double c, double fs, double t0,
-                           int64_t n_samples, const double *rf, int64_t stride,
-                           int nx, int nz, double x0, double dx, double z0, double dz,
-                           int order, double *image)
+ * (x0 + ix*dx, z0 + iz*dz).  weighting: 0 none, 1 coherence factor.
+ * Returns 0 on success, 1 on bad arguments, 2 when out of memory. */
+int hodmas_oracle_beamform_weighted(int n_el, const double *elem_x, double c, double fs, double t0,
+                                    int64_t n_samples, const double *rf, int64_t stride,
+                                    int nx, int nz, double x0, double dx, double z0, double dz,
+                                    int order, int weighting, double *image)
 {
-    if (check_args(n_el, elem_x, c, fs, n_samples, rf, stride, order) || nx < 0 || nz < 0 || !image)
+    if (check_args(n_el, elem_x, c, fs, n_samples, rf, stride, order) || nx < 0 || nz < 0 || !image ||
+        weighting < 0 || weighting > 1)
         return 1;
     int64_t npix = (int64_t)nx * nz;
     int bad = 0;
 #pragma omp parallel
     {
-        double *y = (double *)malloc(sizeof(double) * (size_t)n_el);
+        double *y = (double *)malloc(sizeof(double) * 2 * (size_t)n_el);
         if (!y) {
 #pragma omp atomic write
             bad = 1;
@@ -149,11 +170,21 @@ int hodmas_oracle_beamform(int n_el, const double *elem_x, double c, double fs, 
                 continue;
             int64_t iz = p / nx, ix = p % nx;
             image[p] = beamform_pixel(n_el, elem_x, c, fs, t0, n_samples, rf, stride,
-                                      x0 + (double)ix * dx, z0 + (double)iz * dz, order, y);
+                                      x0 + (double)ix * dx, z0 + (double)iz * dz, order, weighting,
+                                      y, y + n_el);
         }
         free(y);
     }
     return bad ? 2 : 0;
+}
+
+int hodmas_oracle_beamform(int n_el, const double *elem_x, double c, double fs, double t0,
+                           int64_t n_samples, const double *rf, int64_t stride,
+                           int nx, int nz, double x0, double dx, double z0, double dz,
+                           int order, double *image)
+{
+    return hodmas_oracle_beamform_weighted(n_el, elem_x, c, fs, t0, n_samples, rf, stride, nx, nz,
+                                           x0, dx, z0, dz, order, 0, image);
 }
 
 /* A list of pixels (ix[j], iz[j]), j < npix, into out[j]. */
@@ -168,7 +199,7 @@ int hodmas_oracle_beamform_pixels(int n_el, const double *elem_x, double c, doub
     int bad = 0;
 #pragma omp parallel
     {
-        double *y = (double *)malloc(sizeof(double) * (size_t)n_el);
+        double *y = (double *)malloc(sizeof(double) * 2 * (size_t)n_el);
         if (!y) {
 #pragma omp atomic write
             bad = 1;
@@ -178,7 +209,8 @@ int hodmas_oracle_beamform_pixels(int n_el, const double *elem_x, double c, doub
             if (!y)
                 continue;
             out[p] = beamform_pixel(n_el, elem_x, c, fs, t0, n_samples, rf, stride,
-                                    x0 + (double)ix[p] * dx, z0 + (double)iz[p] * dz, order, y);
+                                    x0 + (double)ix[p] * dx, z0 + (double)iz[p] * dz, order, 0,
+                                    y, y + n_el);
         }
         free(y);
     }

@@ -48,6 +48,11 @@ def lib():
         L.hodmas_oracle_beamform.restype = i32
         L.hodmas_oracle_beamform.argtypes = [i32, pd, d, d, d, i64, pd, i64,
                                              i32, i32, d, d, d, d, i32, pd]
+        L.hodmas_oracle_beamform_weighted.restype = i32
+        L.hodmas_oracle_beamform_weighted.argtypes = [i32, pd, d, d, d, i64, pd, i64,
+                                                      i32, i32, d, d, d, d, i32, i32, pd]
+        L.hodmas_oracle_coherence.restype = d
+        L.hodmas_oracle_coherence.argtypes = [pd, i32]
         L.hodmas_oracle_beamform_pixels.restype = i32
         L.hodmas_oracle_beamform_pixels.argtypes = [i32, pd, d, d, d, i64, pd, i64,
                                                     d, d, d, d, i32, i64, pi32, pi32, pd]
@@ -99,8 +104,15 @@ def esym(y, order) -> float:
     return lib().hodmas_oracle_esym(_pd(y), y.shape[0], int(order))
 
 
-def beamform(rf, geometry, grid, order, dequant_scale=None, pixels=None):
+def coherence(v) -> float:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    return lib().hodmas_oracle_coherence(_pd(v), v.shape[0])
+
+
+def beamform(rf, geometry, grid, order, dequant_scale=None, pixels=None, weighting=None):
     """Image [nz][nx] (float64) -- or values at ``pixels`` = (ix, iz) arrays.
+    ``weighting="cf"`` multiplies each pixel by its coherence factor (whole
+    images only).
 
     ``geometry``/``grid`` carry the attributes of ``phantom.Geometry`` /
     ``phantom.Grid`` (duck-typed)."""
@@ -111,12 +123,15 @@ def beamform(rf, geometry, grid, order, dequant_scale=None, pixels=None):
         raise ValueError("element positions do not match the channel count")
     c, fs, t0 = geometry.sound_speed_m_s, geometry.fs_hz, geometry.t0_s
     L = lib()
+    wcode = {None: 0, "cf": 1}[weighting]
     if pixels is None:
         img = np.zeros((grid.nz, grid.nx), dtype=np.float64)
-        rc = L.hodmas_oracle_beamform(n_el, _pd(ex), c, fs, t0, n_s, _pd(x), n_s,
-                                      grid.nx, grid.nz, grid.x0_m, grid.dx_m, grid.z0_m, grid.dz_m,
-                                      int(order), _pd(img))
+        rc = L.hodmas_oracle_beamform_weighted(n_el, _pd(ex), c, fs, t0, n_s, _pd(x), n_s,
+                                               grid.nx, grid.nz, grid.x0_m, grid.dx_m, grid.z0_m,
+                                               grid.dz_m, int(order), wcode, _pd(img))
     else:
+        if wcode:
+            raise ValueError("weighting applies to whole images")
         ix = np.ascontiguousarray(pixels[0], dtype=np.int32)
         iz = np.ascontiguousarray(pixels[1], dtype=np.int32)
         img = np.zeros(ix.shape[0], dtype=np.float64)
