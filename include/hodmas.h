@@ -72,6 +72,8 @@ typedef enum {
 #define HODMAS_FLAG_HOST_ONLY   0x2u  /* build host tables only; no device use (inspection) */
 #define HODMAS_FLAG_FORCE_CHECK 0x4u  /* always run the record-boundary test per sample */
 #define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts */
+#define HODMAS_FLAG_CF          0x10u /* weight each pixel by the coherence factor of its
+                                         delayed samples (hodmas_beamform only) */
 
 /* Linear array.  element_x_m == NULL means a centred uniform array,
  * x_i = (i - (n_elements-1)/2) * pitch_m.  The pointer is read during
@@ -135,7 +137,11 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
  * image_dev: device float32 [nz][nx], fully overwritten.  Both are owned by the
  * caller and must stay valid until the work on `stream` completes.
  * stream: a hipStream_t (NULL = default stream).  Asynchronous; one kernel
- * launch; no allocation.  Errors: EINVAL (null plan/pointers, host-only plan),
+ * launch; no allocation.  With HODMAS_FLAG_CF in the plan each pixel is
+ * multiplied by the coherence factor CF = (sum v)^2 / (N sum v^2) of its N
+ * delayed samples (N the array's element count; CF = 0 when all are 0) --
+ * the coherence-based weighting Sec. VI proposes to combine with these
+ * beamformers.  Errors: EINVAL (null plan/pointers, host-only plan),
  * EUNSUPPORTED (order outside [1, min(6, max_order)]), EDEVICE (launch). */
 hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t order,
                               float* image_dev, void* stream);
@@ -147,7 +153,8 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
  * pointers; images_dev[k-1] (float32 [nz][nx]) receives order k, each fully
  * overwritten.  Results agree with hodmas_beamform to the same tolerance
  * (the roots are formed along different but equivalent routes).  One launch,
- * asynchronous, no allocation.  Errors as for hodmas_beamform; EUNSUPPORTED
+ * asynchronous, no allocation.  Errors as for hodmas_beamform (and
+ * EUNSUPPORTED for a plan with HODMAS_FLAG_CF); EUNSUPPORTED
  * also when the combination of all power sums would not fit the LDS. */
 hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int32_t max_order,
                                      float* const* images_dev, void* stream);
@@ -242,7 +249,8 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
  * at orders[f] from rf[f] (device) into images[f] (device float32 [nz][nx]).
  * Host arrays of n_frames entries, read during the call.  The work list is
  * copied to the device asynchronously on `stream` (launches on the same stream
- * see it).  Errors: EINVAL (null entries, order outside the plan, plan flags,
+ * see it).  Errors: EINVAL (null entries, order outside the plan, plan flags
+ * -- including HODMAS_FLAG_CF, which the batch kernels do not carry --
  * host-only or other-device plan, too many frames/units, plan LDS above the
  * batch's bound or a workgroup other than 256 threads), EUNSUPPORTED, EDEVICE. */
 hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,

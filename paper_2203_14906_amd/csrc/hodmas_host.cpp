@@ -310,8 +310,10 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     }
     // LDS: `chunk` windows of `max_window` floats; shrink the chunk until it fits.
     const int64_t block = int64_t(p->tiling.tile_x) * p->tiling.tile_z * p->tiling.split;
+    // split-group combination: (sum, compensation) of up to MAX_ORDER power
+    // sums plus the two coherence-factor sums per pixel
     const int64_t reduce_bytes = int64_t(block / p->tiling.split) * (p->tiling.split - 1) *
-                                 HODMAS_MAX_ORDER * 2 * 4;
+                                 (HODMAS_MAX_ORDER + 2) * 2 * 4;
     // 40 KB keeps four workgroups on a CU (160 KB); an explicit chunk may use 64 KB
     const int64_t cap = auto_chunk ? 40 * 1024 : 64 * 1024;
     if (int64_t(p->max_window) * 4 > hodmas::kMaxLdsBytes) {
@@ -361,6 +363,7 @@ FrameArgs hodmas::frame_args(const hodmas_plan_s* plan, const void* rf_dev, floa
     a.split = plan->tiling.split;
     a.chunk = plan->tiling.chunk;
     a.n_tiles = (int32_t)plan->tiles.size();
+    a.n_elements = plan->geom.n_elements;
     a.block = plan->tiling.tile_x * plan->tiling.tile_z * plan->tiling.split;
     a.x0s = plan->x0s;
     a.dxs = plan->dxs;
@@ -389,7 +392,8 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
         return HODMAS_EDEVICE;
     const FrameArgs a = hodmas::frame_args(plan, rf_dev, image_dev);
     const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
-    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, plan->lds_bytes, stream);
+    const bool cf = (plan->flags & HODMAS_FLAG_CF) != 0;
+    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, cf, plan->lds_bytes, stream);
     if (cur != plan->device)
         (void)hipSetDevice(cur);
     return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
@@ -402,7 +406,8 @@ hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int
         return HODMAS_EINVAL;
     if (plan->flags & HODMAS_FLAG_HOST_ONLY)
         return HODMAS_EINVAL;
-    if (max_order < 1 || max_order > plan->max_order || max_order > HODMAS_MAX_ORDER)
+    if (max_order < 1 || max_order > plan->max_order || max_order > HODMAS_MAX_ORDER ||
+        (plan->flags & HODMAS_FLAG_CF))
         return HODMAS_EUNSUPPORTED;
     hodmas::OrderImages out{};
     for (int k = 0; k < max_order; ++k) {

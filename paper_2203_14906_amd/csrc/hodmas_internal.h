@@ -27,6 +27,7 @@ struct FrameArgs {
     int32_t nx, nz;
     int32_t tile_x, split, chunk;
     int32_t n_tiles;
+    int32_t n_elements;      // array elements (the coherence factor's N)
     int32_t block;           // threads per workgroup: tile_x * tile_z * split
     double x0s, dxs, z0s, dzs;  // grid in samples
     float in_scale;          // stored value -> kernel value (dequant / frame_max)
@@ -65,8 +66,8 @@ struct BatchUnit {
 };
 
 // Launch one frame on `stream`.  Returns hipSuccess or the launch error code.
-int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, int64_t lds_bytes,
-                 void* stream);
+int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, bool coherence,
+                 int64_t lds_bytes, void* stream);
 
 constexpr uint32_t kPlanMagic = 0x484f444du;  // "HODM"
 

@@ -157,6 +157,25 @@ __device__ __forceinline__ void powers(float v, float (&T)[K])
     }
 }
 
+// The sums one element feeds: y^1 .. y^K, then -- with coherence-factor
+// weighting -- the sample itself and its square.
+template <int K, bool CF>
+constexpr int n_sums() { return K + (CF ? 2 : 0); }
+
+template <int K, bool CF>
+__device__ __forceinline__ void terms(float v, float (&T)[n_sums<K, CF>()])
+{
+    float Y[K];
+    powers<K>(v, Y);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        T[j] = Y[j];
+    if constexpr (CF) {
+        T[K] = v;
+        T[K + 1] = v * v;
+    }
+}
+
 template <int DT>
 __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, int nch, int window,
                                             float* __restrict__ lds, int wave, int nwaves, int lane)
@@ -237,9 +256,9 @@ __device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[
 // in -- the scalar loads of the next group's constants (the LDS/scalar wait
 // counter does not order scalar loads, so issuing them earlier would make
 // this group's waits also wait for them), then roots, powers and the sums.
-template <int K, bool COMP, bool CHECK>
+template <int K, bool CF, bool COMP, bool CHECK, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], float u2, float q,
-                                              const float* __restrict__ lds, float (&s)[K], float (&P)[K],
+                                              const float* __restrict__ lds, float (&s)[NS], float (&P)[NS],
                                               bool more, ConstEntry En, hodmas_chan_entry (&en)[4])
 {
     Tap tp[4];
@@ -260,12 +279,12 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
     asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]) : "memory");
     if (more)
         load_group(En, en);
-    float T[4][K];
+    float T[4][NS];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        powers<K>(v[m], T[m]);
+        terms<K, CF>(v[m], T[m]);
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < NS; ++j) {
         if (COMP) {
             P[j] += (T[0][j] + T[1][j]) + (T[2][j] + T[3][j]);
         } else {
@@ -287,13 +306,13 @@ __device__ __forceinline__ void after_group(int& groups, float (&s)[K], float (&
 // The n elements of this wave's split group in one staged chunk (their
 // constants stored contiguously), four at a time; two constant sets alternate
 // so nothing is copied between them.
-template <int K, bool COMP, bool CHECK>
+template <int K, bool CF, bool COMP, bool CHECK, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, float q,
-                                                 const float* __restrict__ lds, float (&s)[K], float (&c)[K])
+                                                 const float* __restrict__ lds, float (&s)[NS], float (&c)[NS])
 {
-    float P[K];
+    float P[NS];
 #pragma unroll
-    for (int j = 0; j < K; ++j)
+    for (int j = 0; j < NS; ++j)
         P[j] = 0.f;
     int sl = 0;
     if (n >= 4) {
@@ -302,14 +321,14 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group<K, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
-            after_group<K, COMP>(groups, s, c, P);
+            process_group<K, CF, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
+            after_group<NS, COMP>(groups, s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group<K, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
-            after_group<K, COMP>(groups, s, c, P);
+            process_group<K, CF, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
+            after_group<NS, COMP>(groups, s, c, P);
             sl += 4;
             if (!more_b)
                 break;
@@ -318,10 +337,10 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
     for (; sl < n; ++sl) {
         const hodmas_chan_entry e = load_const(E, sl);
         const Tap tp = locate(e, u2, q);
-        float T[K];
-        powers<K>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
+        float T[NS];
+        terms<K, CF>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
+        for (int j = 0; j < NS; ++j) {
             if (COMP)
                 P[j] += T[j];
             else
@@ -329,7 +348,7 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         }
     }
     if (COMP)
-        flush<K>(s, c, P);
+        flush<NS>(s, c, P);
 }
 
 // Newton's identities: e_m = (1/m) sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
@@ -354,9 +373,10 @@ __device__ __forceinline__ R newton(const R (&p)[K])
 // One pixel tile of one frame: stage, accumulate, combine, recover, store.
 // Every thread of the workgroup calls this with the same (A, tile); all
 // branches on tile data are workgroup-uniform, so the barriers inside match.
-template <int K, int DT, bool COMP>
+template <int K, int DT, bool COMP, bool CF = false>
 __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
 {
+    constexpr int NS = n_sums<K, CF>();
     const hodmas_tile_desc td = load_const(A.tiles, tile);
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
@@ -384,9 +404,9 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     const float u2 = (float)(2.0 * u);
     const float q = (float)(u * u + w * (w + 2.0 * td.za));
 
-    float s[K], c[K];
+    float s[NS], c[NS];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
+    for (int j = 0; j < NS; ++j) {
         s[j] = 0.f;
         c[j] = 0.f;
     }
@@ -403,9 +423,9 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
         if (td.check)
-            accumulate_chunk<K, COMP, true>(E + c0 + goff, ng, u2, q, lds, s, c);
+            accumulate_chunk<K, CF, COMP, true>(E + c0 + goff, ng, u2, q, lds, s, c);
         else
-            accumulate_chunk<K, COMP, false>(E + c0 + goff, ng, u2, q, lds, s, c);
+            accumulate_chunk<K, CF, COMP, false>(E + c0 + goff, ng, u2, q, lds, s, c);
     }
 
     if (A.split > 1) {
@@ -414,18 +434,18 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
         float* red = lds;
         if (g > 0) {
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                red[((g - 1) * npix + pl) * 2 * K + 2 * j] = s[j];
-                red[((g - 1) * npix + pl) * 2 * K + 2 * j + 1] = c[j];
+            for (int j = 0; j < NS; ++j) {
+                red[((g - 1) * npix + pl) * 2 * NS + 2 * j] = s[j];
+                red[((g - 1) * npix + pl) * 2 * NS + 2 * j + 1] = c[j];
             }
         }
         __syncthreads();
         if (g == 0) {
             for (int gg = 1; gg < A.split; ++gg) {
 #pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    const float so = red[((gg - 1) * npix + pl) * 2 * K + 2 * j];
-                    const float co = red[((gg - 1) * npix + pl) * 2 * K + 2 * j + 1];
+                for (int j = 0; j < NS; ++j) {
+                    const float so = red[((gg - 1) * npix + pl) * 2 * NS + 2 * j];
+                    const float co = red[((gg - 1) * npix + pl) * 2 * NS + 2 * j + 1];
                     if (COMP) {
                         kahan_add(s[j], c[j], so);
                         kahan_add(s[j], c[j], -co);
@@ -444,14 +464,22 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     for (int j = 0; j < K; ++j)
         p[j] = COMP ? R(s[j]) - R(c[j]) : R(s[j]);
     const R ek = newton<K, R>(p);
-    *dst = (float)(ek * R(A.out_scale));
+    if constexpr (CF) {
+        // coherence factor (sum v)^2 / (N sum v^2) of the normalised samples
+        const double s1 = COMP ? double(s[K]) - double(c[K]) : double(s[K]);
+        const double s2 = COMP ? double(s[K + 1]) - double(c[K + 1]) : double(s[K + 1]);
+        const double cf = s2 > 0.0 ? (s1 * s1) / (double(A.n_elements) * s2) : 0.0;
+        *dst = (float)(double(ek) * cf * double(A.out_scale));
+    } else {
+        *dst = (float)(ek * R(A.out_scale));
+    }
 }
 
-template <int K, int DT, bool COMP>
+template <int K, int DT, bool COMP, bool CF>
 __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 {
     extern __shared__ float lds[];
-    process_tile<K, DT, COMP>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
+    process_tile<K, DT, COMP, CF>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
 }
 
 // Persistent form: one kernel per (order, storage type).  Its fixed grid walks
@@ -795,40 +823,44 @@ int launch_orders_dt(const FrameArgs& a, const OrderImages& out, int kmax, bool 
 }
 
 template <int K, int DT>
-int launch_k(const FrameArgs& a, bool comp, int64_t lds_bytes, hipStream_t st)
+int launch_k(const FrameArgs& a, bool comp, bool cf, int64_t lds_bytes, hipStream_t st)
 {
     dim3 grid(a.n_tiles), block(a.block);
-    if (comp)
-        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true>), grid, block, (size_t)lds_bytes, st, a);
+    if (comp && cf)
+        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true, true>), grid, block, (size_t)lds_bytes, st, a);
+    else if (comp)
+        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true, false>), grid, block, (size_t)lds_bytes, st, a);
+    else if (cf)
+        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, false, true>), grid, block, (size_t)lds_bytes, st, a);
     else
-        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, false>), grid, block, (size_t)lds_bytes, st, a);
+        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, false, false>), grid, block, (size_t)lds_bytes, st, a);
     return (int)hipGetLastError();
 }
 
 template <int DT>
-int launch_dt(const FrameArgs& a, int order, bool comp, int64_t lds_bytes, hipStream_t st)
+int launch_dt(const FrameArgs& a, int order, bool comp, bool cf, int64_t lds_bytes, hipStream_t st)
 {
     switch (order) {
-    case 1: return launch_k<1, DT>(a, comp, lds_bytes, st);
-    case 2: return launch_k<2, DT>(a, comp, lds_bytes, st);
-    case 3: return launch_k<3, DT>(a, comp, lds_bytes, st);
-    case 4: return launch_k<4, DT>(a, comp, lds_bytes, st);
-    case 5: return launch_k<5, DT>(a, comp, lds_bytes, st);
-    case 6: return launch_k<6, DT>(a, comp, lds_bytes, st);
+    case 1: return launch_k<1, DT>(a, comp, cf, lds_bytes, st);
+    case 2: return launch_k<2, DT>(a, comp, cf, lds_bytes, st);
+    case 3: return launch_k<3, DT>(a, comp, cf, lds_bytes, st);
+    case 4: return launch_k<4, DT>(a, comp, cf, lds_bytes, st);
+    case 5: return launch_k<5, DT>(a, comp, cf, lds_bytes, st);
+    case 6: return launch_k<6, DT>(a, comp, cf, lds_bytes, st);
     }
     return (int)hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, int64_t lds_bytes,
-                 void* stream)
+int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, bool coherence,
+                 int64_t lds_bytes, void* stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (dtype) {
-    case HODMAS_F32: return launch_dt<HODMAS_F32>(a, order, compensated, lds_bytes, st);
-    case HODMAS_F16: return launch_dt<HODMAS_F16>(a, order, compensated, lds_bytes, st);
-    case HODMAS_I16: return launch_dt<HODMAS_I16>(a, order, compensated, lds_bytes, st);
+    case HODMAS_F32: return launch_dt<HODMAS_F32>(a, order, compensated, coherence, lds_bytes, st);
+    case HODMAS_F16: return launch_dt<HODMAS_F16>(a, order, compensated, coherence, lds_bytes, st);
+    case HODMAS_I16: return launch_dt<HODMAS_I16>(a, order, compensated, coherence, lds_bytes, st);
     }
     return (int)hipErrorInvalidValue;
 }
