@@ -330,6 +330,37 @@ hodmas_status hodmas_display_run(hodmas_display_t display, const float* image_de
 /* Release a display plan.  NULL is accepted. */
 hodmas_status hodmas_display_destroy(hodmas_display_t display);
 
+/* -------------------------------------------------------------------------
+ * Image-quality metrics (Sec. IV): SNR = 20 log10(mu_in / sigma_out)
+ * (Eq. 10), CR = 20 log10(mu_in / mu_out) (Eq. 11) and
+ * gCNR = 1 - sum_x min(h_in(x), h_out(x)) (Eq. 12) over a target and a
+ * background rectangle of an envelope image, and the FWHM of the target's
+ * lateral profile.  Readings: population standard deviation; amplitudes
+ * normalised by the largest value over both regions and binned into `bins`
+ * equal bins on [0, 1] (top edge in the last bin, negatives in the first),
+ * each histogram divided by its pixel count; FWHM along the image row through
+ * the target's first maximum (row-major), walking out to the first samples at
+ * or below half of it with linear interpolation (a side that never gets there
+ * ends at the image edge), times dx_m.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t ix0, ix1, iz0, iz1;  /* pixels [ix0, ix1) x [iz0, iz1) */
+} hodmas_rect;
+
+typedef struct {
+    double snr_db, cr_db, gcnr, fwhm_m;
+    double mu_in, mu_out, sigma_out;
+} hodmas_metrics;
+
+/* image_dev: device float32 [nz][nx].  Runs one workgroup on `stream`, waits
+ * for it and fills *out (host).  Allocates and frees a few bytes of device
+ * memory: an evaluation call, not for the hot path.  Errors: EINVAL (null
+ * pointers, empty or out-of-image rectangles, dx_m <= 0, bins outside
+ * 2..4096), ENOMEM, EDEVICE. */
+hodmas_status hodmas_image_metrics(const float* image_dev, int32_t nx, int32_t nz, double dx_m,
+                                   const hodmas_rect* target, const hodmas_rect* background,
+                                   int32_t bins, void* stream, hodmas_metrics* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,8 +13,9 @@ Readings (the paper gives no further detail): the metrics are taken on the
 envelope image (linear amplitude); regions are pixel rectangles
 [ix0, ix1) x [iz0, iz1); sigma_out is the population standard deviation; the
 amplitude is normalised by the largest value over both regions and binned
-into B equal bins on [0, 1] (the top edge in the last bin), each histogram
-divided by its region's pixel count; the FWHM is taken along the image row
+into B equal bins on [0, 1] (the top edge in the last bin, a negative value
+-- not expected of an envelope -- in the first), each histogram divided by
+its region's pixel count; the FWHM is taken along the image row
 through the target region's maximum, walking left and right from the peak to
 the first samples at or below half of it and interpolating linearly between
 neighbouring pixels, times the pixel pitch (a side that never drops to half
@@ -44,7 +45,7 @@ def gcnr(img, target, background, bins: int = 256) -> float:
     if peak <= 0.0:
         return 0.0
     def hist(r):
-        idx = np.minimum((r / peak * bins).astype(np.int64), bins - 1)
+        idx = np.clip((r / peak * bins).astype(np.int64), 0, bins - 1)
         return np.bincount(idx.ravel(), minlength=bins) / r.size
     return 1.0 - np.minimum(hist(t), hist(b)).sum()
 

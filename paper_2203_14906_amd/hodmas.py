@@ -85,6 +85,17 @@ class StageEntry(ctypes.Structure):
     _fields_ = [("channel", ctypes.c_int32), ("first_sample", ctypes.c_int32)]
 
 
+class Rect(ctypes.Structure):
+    _fields_ = [("ix0", ctypes.c_int32), ("ix1", ctypes.c_int32), ("iz0", ctypes.c_int32),
+                ("iz1", ctypes.c_int32)]
+
+
+class Metrics(ctypes.Structure):
+    _fields_ = [("snr_db", ctypes.c_double), ("cr_db", ctypes.c_double), ("gcnr", ctypes.c_double),
+                ("fwhm_m", ctypes.c_double), ("mu_in", ctypes.c_double), ("mu_out", ctypes.c_double),
+                ("sigma_out", ctypes.c_double)]
+
+
 class DisplayDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("dz_m", ctypes.c_double),
                 ("sound_speed_m_s", ctypes.c_double), ("f_lo_hz", ctypes.c_double),
@@ -153,6 +164,9 @@ def _load():
     L.hodmas_display_run.argtypes = [vp, vp, vp, vp, vp]
     L.hodmas_display_destroy.restype = i32
     L.hodmas_display_destroy.argtypes = [vp]
+    L.hodmas_image_metrics.restype = i32
+    L.hodmas_image_metrics.argtypes = [vp, i32, i32, ctypes.c_double, ctypes.POINTER(Rect), ctypes.POINTER(Rect),
+                                       i32, vp, ctypes.POINTER(Metrics)]
     return L
 
 
@@ -425,3 +439,17 @@ class Display:
             self.close()
         except Exception:
             pass
+
+
+def image_metrics(image, dx_m, target, background, bins=256, stream=None):
+    """SNR, CR, gCNR and FWHM of an envelope image (a [nz][nx] float32 GPU
+    tensor); target and background are (ix0, ix1, iz0, iz1) pixel rectangles."""
+    import torch
+    if image.dtype != torch.float32 or not image.is_cuda or not image.is_contiguous() or image.dim() != 2:
+        raise ValueError("image must be a contiguous float32 GPU tensor [nz][nx]")
+    nz, nx = image.shape
+    t, b, m = Rect(*[int(v) for v in target]), Rect(*[int(v) for v in background]), Metrics()
+    _check(lib.hodmas_image_metrics(ctypes.c_void_p(image.data_ptr()), int(nx), int(nz), float(dx_m),
+                                    ctypes.byref(t), ctypes.byref(b), int(bins), _stream_handle(stream),
+                                    ctypes.byref(m)), "hodmas_image_metrics")
+    return {f: getattr(m, f) for f, _ in Metrics._fields_}
