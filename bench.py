@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=8, help="frames per step")
     ap.add_argument("--orders", default="1,2,3,4,5,6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="plain: skip the batched-launch comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
@@ -176,6 +177,31 @@ def bench_plain(args, torch):
                  "frac": round(f_ach / VALU_PEAK_TSLOT, 4),
                  "traffic": _profiled_traffic("hodmas_orders_kernel<%d, f32, comp>" % kmax)}
 
+    # the same step through one persistent batch launch per order (the batch
+    # form's workgroups drift out of step, so one tile's staging overlaps
+    # another's arithmetic)
+    batched = None
+    if not args.no_batched and info.tiling.tile_x * info.tiling.tile_z * info.tiling.split == 256:
+        bt = hodmas.Batch(max_frames=args.batch, max_units=info.n_tiles * args.batch, max_lds_bytes=info.lds_bytes)
+        b_us = {}
+        for k in orders:
+            bt.set([plan] * args.batch, rf_dev, [k] * args.batch, out)
+            for _ in range(max(1, args.warmup)):
+                bt.launch(stream=stream)
+            bev = _events(torch, args.steps)
+            torch.cuda.synchronize()
+            for s_ in range(args.steps):
+                bev[s_][0].record(stream)
+                bt.launch(stream=stream)
+                bev[s_][1].record(stream)
+            torch.cuda.synchronize()
+            b_us[k] = sum(a.elapsed_time(z) for a, z in bev) / (args.steps * args.batch) * 1e3
+        b_tot = sum(b_us.values())
+        batched = {"kernel_us_per_frame": {str(k): round(v, 2) for k, v in b_us.items()},
+                   "gpixch_s_sum_orders": round(pixch * len(orders) / (b_tot * 1e-6) / 1e9, 2),
+                   "speedup_vs_per_frame_launches": round(sum(per_order_ms.values()) * 1e3 / b_tot, 3)}
+        bt.close()
+
     # relative L2 of the last images against the oracle is checked by the tests;
     # here only the CPU oracle's throughput on the same batch is measured.
     cpu = None
@@ -216,6 +242,7 @@ def bench_plain(args, torch):
         "per_order_gpixch_s": per_order,
         "per_order_kernel_us": {str(k): round(per_order_ms[k] * 1e3, 2) for k in orders},
         "fused_all_orders": fused,
+        "batched_per_order": batched,
         "roofline": {"bound": "alu", "kernel": dom_kernel,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),
