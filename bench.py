@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--orders", default="1,2,3,4,5,6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="plain: skip the batched-launch comparison")
+    ap.add_argument("--no-tune", action="store_true", help="batch: default tilings instead of the autotuner's")
+    ap.add_argument("--tune-cache", default=os.path.join("/tmp", "hodmas_tune_cache.jsonl"),
+                    help="batch: autotuner cache file (JSON lines)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
@@ -305,9 +308,11 @@ def bench_reduced(args, torch):
     print(json.dumps(res))
 
 
-def _mixed_frames(torch, specs, with_fp32):
+def _mixed_frames(torch, specs, with_fp32, tune_cache=None):
     """Device-resident frames of the mixed workload; the RF of each (N, S)
-    shape comes from one seeded phantom shared by the frames of that shape."""
+    shape comes from one seeded phantom shared by the frames of that shape.
+    With ``tune_cache`` the FP16 plans take the autotuner's tiling (tuned at
+    order 6 among the tilings a batch accepts, cached in that file)."""
     from paper_2203_14906_amd import hodmas, phantom as ph
     rf_cache, plans, frames = {}, {}, []
     for sp in specs:
@@ -320,7 +325,11 @@ def _mixed_frames(torch, specs, with_fp32):
             w, d = ph.field_of_view(n, S)
             grid = ph.make_grid(side, side, w, d)
             geom = ph.Geometry(n)
-            plans[(n, S, side)] = (hodmas.Plan(geom, grid, S, "f16", max_order=6),
+            tiling = None
+            if tune_cache is not None:
+                tiling = hodmas.autotune(geom, grid, S, "f16", 6, flags=hodmas.FLAG_TUNE_BATCH,
+                                         cache_path=tune_cache)
+            plans[(n, S, side)] = (hodmas.Plan(geom, grid, S, "f16", max_order=6, tiling=tiling),
                                    hodmas.Plan(geom, grid, S, "f32", max_order=6) if with_fp32 else None)
         frames.append(dict(spec=sp, rf16=rf_cache[(n, S)][0], rf32=rf_cache[(n, S)][1],
                            plan16=plans[(n, S, side)][0], plan32=plans[(n, S, side)][1],
@@ -336,7 +345,10 @@ def bench_batch(args, torch):
     import numpy as np
     from paper_2203_14906_amd import hodmas, phantom as ph
     specs = ph.mixed_batch_specs(256, seed=4000)
-    frames, plans = _mixed_frames(torch, specs, with_fp32=True)
+    t_tune = time.perf_counter()
+    frames, plans = _mixed_frames(torch, specs, with_fp32=True,
+                                  tune_cache=None if args.no_tune else args.tune_cache)
+    t_tune = time.perf_counter() - t_tune
     outs_b = [torch.empty((f["spec"]["side"],) * 2, dtype=torch.float32, device="cuda") for f in frames]
     outs_p = [torch.empty_like(o) for o in outs_b]
     orders = [f["spec"]["order"] for f in frames]
@@ -381,7 +393,9 @@ def bench_batch(args, torch):
            "unit": "frames/s", "n_gpus": 1, "data": "synthetic", "dtype": "f16 storage / f32 compute",
            "config": {"workload": "256 mixed frames: N in {64,128,256}, S in {1024,2048,4096}, "
                                   "grid side in {256,512,768,1024}, order 1..6, seed 4000",
-                      "units": inf.n_units, "grid": inf.grid, "lds_bytes": inf.lds_bytes},
+                      "units": inf.n_units, "grid": inf.grid, "lds_bytes": inf.lds_bytes,
+                      "tilings": "autotuned" if not args.no_tune else "default",
+                      "setup_s_incl_tuning": round(t_tune, 1)},
            "batched": {"frames_per_s": round(256 / (tb_ms * 1e-3), 1), "batch_ms": round(tb_ms, 3),
                        "p50_ms": round(tb_ms, 3), "p99_ms": round(tb_ms, 3),
                        "gpixch_s": round(pixch / (tb_ms * 1e-3) / 1e9, 1)},
