@@ -55,9 +55,10 @@ def parse():
     ap.add_argument("--orders", default="1,2,3,4,5,6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="plain: skip the batched-launch comparison")
+    ap.add_argument("--no-mirror", action="store_true", help="plain: skip the mirror-paired comparison")
     ap.add_argument("--no-tune", action="store_true", help="batch: default tilings instead of the autotuner's")
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "hodmas_tune_cache.jsonl"),
-                    help="batch: autotuner cache file (JSON lines)")
+                    help="batch and plain mirror pairs: autotuner cache file (JSON lines)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
@@ -205,6 +206,35 @@ def bench_plain(args, torch):
                    "speedup_vs_per_frame_launches": round(sum(per_order_ms.values()) * 1e3 / b_tot, 3)}
         bt.close()
 
+    # mirror pairing: the array and the grid are symmetric about x = 0, so one
+    # workgroup forms a tile and its mirror image from one set of delays
+    # (HODMAS_FLAG_MIRROR); tiling per order from the autotuner
+    mirrored = None
+    if not args.no_mirror:
+        m_us, m_tiling = {}, {}
+        for k in orders:
+            t = hodmas.autotune(geom, grid, S, "f32", k, flags=hodmas.FLAG_MIRROR, cache_path=args.tune_cache)
+            mp = hodmas.Plan(geom, grid, S, "f32", max_order=k, tiling=t, flags=hodmas.FLAG_MIRROR)
+            for _ in range(max(1, args.warmup)):
+                for b in range(args.batch):
+                    mp.beamform(rf_dev[b], k, out[b], stream=stream)
+            mev = _events(torch, args.steps)
+            torch.cuda.synchronize()
+            for s_ in range(args.steps):
+                mev[s_][0].record(stream)
+                for b in range(args.batch):
+                    mp.beamform(rf_dev[b], k, out[b], stream=stream)
+                mev[s_][1].record(stream)
+            torch.cuda.synchronize()
+            m_us[k] = sum(a.elapsed_time(z) for a, z in mev) / (args.steps * args.batch) * 1e3
+            mt = mp.info().tiling
+            m_tiling[str(k)] = [mt.tile_x, mt.tile_z, mt.split, mt.chunk]
+            mp.close()
+        mirrored = {"kernel": "hodmas_frame_kernel<k, f32, comp, mirror pairs>",
+                    "kernel_us_per_frame": {str(k): round(v, 2) for k, v in m_us.items()},
+                    "tilings": m_tiling,
+                    "speedup_vs_unpaired": {str(k): round(per_order_ms[k] * 1e3 / m_us[k], 3) for k in orders}}
+
     # relative L2 of the last images against the oracle is checked by the tests;
     # here only the CPU oracle's throughput on the same batch is measured.
     cpu = None
@@ -246,6 +276,7 @@ def bench_plain(args, torch):
         "per_order_kernel_us": {str(k): round(per_order_ms[k] * 1e3, 2) for k in orders},
         "fused_all_orders": fused,
         "batched_per_order": batched,
+        "mirror_paired": mirrored,
         "roofline": {"bound": "alu", "kernel": dom_kernel,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),

@@ -74,6 +74,9 @@ typedef enum {
 #define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts */
 #define HODMAS_FLAG_CF          0x10u /* weight each pixel by the coherence factor of its
                                          delayed samples (hodmas_beamform only) */
+#define HODMAS_FLAG_MIRROR      0x20u /* hodmas_beamform forms each pixel together with
+                                         its mirror image about x = 0 from one delay
+                                         (symmetric array and grid only, see hodmas_plan) */
 
 /* Linear array.  element_x_m == NULL means a centred uniform array,
  * x_i = (i - (n_elements-1)/2) * pitch_m.  The pointer is read during
@@ -126,8 +129,14 @@ typedef struct hodmas_plan_s* hodmas_plan_t;
  * max_order in [1, HODMAS_MAX_ORDER].  tiling may be NULL (library default).
  * Pixels must lie in front of the array (z0_m > 0, dz_m > 0) and dx_m > 0.
  * On success *out owns its device tables until hodmas_destroy.
+ * HODMAS_FLAG_MIRROR needs an array and a grid symmetric about x = 0
+ * (x_i = -x_{n-1-i} and x0_m = -(nx-1) dx_m / 2, each to 1e-6 of a sample
+ * length c/fs) and a tiling whose tile_x divides nx into an even number of
+ * tile columns; hodmas_beamform then runs one workgroup per pair of mirror
+ * tiles.  Images differ from the unpaired launch only in rounding.
  * Errors: EINVAL (null pointer, non-positive or non-finite sizes/speeds, stride
- * < S, limits above exceeded, bad tiling), ENOMEM, EDEVICE. */
+ * < S, limits above exceeded, bad tiling, HODMAS_FLAG_MIRROR on an asymmetric
+ * geometry or tiling), ENOMEM, EDEVICE. */
 hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* grid,
                           const hodmas_rf_desc* rf, int32_t max_order, uint32_t flags,
                           const hodmas_tiling* tiling, hodmas_plan_t* out);
@@ -250,7 +259,8 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
  * Host arrays of n_frames entries, read during the call.  The work list is
  * copied to the device asynchronously on `stream` (launches on the same stream
  * see it).  Errors: EINVAL (null entries, order outside the plan, plan flags
- * -- including HODMAS_FLAG_CF, which the batch kernels do not carry --
+ * -- including HODMAS_FLAG_CF and HODMAS_FLAG_MIRROR, which the batch
+ * kernels do not carry --
  * host-only or other-device plan, too many frames/units, plan LDS above the
  * batch's bound or a workgroup other than 256 threads), EUNSUPPORTED, EDEVICE. */
 hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,

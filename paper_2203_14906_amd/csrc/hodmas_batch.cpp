@@ -157,8 +157,8 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
             const hodmas_plan_s* p = plans[f];
             if (!p || p->magic != hodmas::kPlanMagic || !rf[f] || !images[f])
                 return HODMAS_EINVAL;
-            if ((p->flags & (HODMAS_FLAG_HOST_ONLY | HODMAS_FLAG_CF)) || p->device != b->device)
-                return HODMAS_EINVAL;   // the batch kernels carry no coherence weighting
+            if ((p->flags & (HODMAS_FLAG_HOST_ONLY | HODMAS_FLAG_CF | HODMAS_FLAG_MIRROR)) || p->device != b->device)
+                return HODMAS_EINVAL;   // no coherence weighting or mirror pairing in the batch kernels
             if ((p->flags & HODMAS_FLAG_ACC_PLAIN) != (b->flags & HODMAS_FLAG_ACC_PLAIN))
                 return HODMAS_EINVAL;
             if (orders[f] < 1 || orders[f] > p->max_order)

@@ -84,18 +84,34 @@ hodmas_status validate(const hodmas_geometry* g, const hodmas_grid* gr, const ho
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Mirror pairing needs whole tile columns, an even number of them.
+bool mirror_columns(int32_t nx, int32_t tile_x) { return nx % tile_x == 0 && (nx / tile_x) % 2 == 0; }
+
 // Library default: 16x16 pixel tiles; split the channels of a pixel over 2 or 4
-// waves when the grid has too few tiles to give every CU a few workgroups.
-hodmas_tiling default_tiling(const hodmas_grid& gr)
+// waves when the grid has too few tiles (pairs of tiles, when mirrored) to give
+// every CU a few workgroups.  Mirrored grids that 16 does not divide into an
+// even number of columns get 8-pixel-wide tiles.
+hodmas_tiling default_tiling(const hodmas_grid& gr, bool mirror)
 {
     const int64_t want = 2 * 256;  // two workgroups per CU
-    hodmas_tiling t{16, 16, 1, 0};
-    if (ceil_div(gr.nx, 16) * ceil_div(gr.nz, 16) >= want)
-        return t;
-    t = {16, 8, 2, 0};
-    if (ceil_div(gr.nx, 16) * ceil_div(gr.nz, 8) >= want)
-        return t;
-    return {8, 8, 4, 0};
+    const int per_wg = mirror ? 2 : 1;
+    const int tx = (mirror && !mirror_columns(gr.nx, 16)) ? 8 : 16;
+    const hodmas_tiling cand[2] = {{tx, 256 / tx, 1, 0}, {tx, 128 / tx, 2, 0}};
+    for (const hodmas_tiling& t : cand)
+        if (ceil_div(gr.nx, t.tile_x) * ceil_div(gr.nz, t.tile_z) / per_wg >= want)
+            return t;
+    return {tx, 64 / tx, 4, 0};
+}
+
+// The array and the grid are mirror images of themselves about x = 0, to
+// `tol` metres.
+bool symmetric(const hodmas_plan_s* p, double tol)
+{
+    const int n = p->geom.n_elements;
+    for (int i = 0; i < n; ++i)
+        if (!(std::fabs(p->elem_x[i] + p->elem_x[n - 1 - i]) <= tol))
+            return false;
+    return std::fabs(2.0 * p->grid.x0_m + (p->grid.nx - 1) * p->grid.dx_m) <= 2.0 * tol;
 }
 
 void free_device(hodmas_plan_s* p)
@@ -297,7 +313,16 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
                            ? geometry->element_x_m[i]
                            : (i - (geometry->n_elements - 1) / 2.0) * geometry->pitch_m;
     bool given = tiling && (tiling->tile_x || tiling->tile_z || tiling->split || tiling->chunk);
-    p->tiling = given ? *tiling : default_tiling(*grid);
+    const bool mirror = (flags & HODMAS_FLAG_MIRROR) != 0;
+    p->tiling = given ? *tiling : default_tiling(*grid, mirror);
+    if (mirror) {
+        const double lam = geometry->sound_speed_m_s / geometry->fs_hz;
+        if (!mirror_columns(grid->nx, p->tiling.tile_x) || !symmetric(p, 1e-6 * lam)) {
+            delete p;
+            return HODMAS_EINVAL;
+        }
+    }
+    const int rows = mirror ? 2 : 1;   // LDS rows per staged slot (own, mirrored)
     // chunk 0: every element at once for now; the windows (which do not depend
     // on the chunk) then decide how many fit the LDS budget
     const bool auto_chunk = p->tiling.chunk == 0;
@@ -313,15 +338,15 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     // split-group combination: (sum, compensation) of up to MAX_ORDER power
     // sums plus the two coherence-factor sums per pixel
     const int64_t reduce_bytes = int64_t(block / p->tiling.split) * (p->tiling.split - 1) *
-                                 (HODMAS_MAX_ORDER + 2) * 2 * 4;
+                                 (HODMAS_MAX_ORDER + 2) * 2 * 4 * rows;
     // 40 KB keeps four workgroups on a CU (160 KB); an explicit chunk may use 64 KB
     const int64_t cap = auto_chunk ? 40 * 1024 : 64 * 1024;
-    if (int64_t(p->max_window) * 4 > hodmas::kMaxLdsBytes) {
+    if (int64_t(p->max_window) * 4 * rows > hodmas::kMaxLdsBytes) {
         delete p;
         return HODMAS_EUNSUPPORTED;
     }
-    if (int64_t(p->tiling.chunk) * p->max_window * 4 > cap) {
-        int c = (int)std::max<int64_t>(1, cap / (int64_t(p->max_window) * 4));
+    if (int64_t(p->tiling.chunk) * p->max_window * 4 * rows > cap) {
+        int c = (int)std::max<int64_t>(1, cap / (int64_t(p->max_window) * 4 * rows));
         p->tiling.chunk = c;
         st = build_tables(p);  // entry offsets depend on the chunk
         if (st != HODMAS_OK) {
@@ -329,7 +354,7 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
             return st;
         }
     }
-    p->lds_bytes = std::max<int64_t>(int64_t(p->tiling.chunk) * p->max_window * 4, reduce_bytes);
+    p->lds_bytes = std::max<int64_t>(int64_t(p->tiling.chunk) * p->max_window * 4 * rows, reduce_bytes);
     const double fm = rf->frame_max > 0.f ? (double)rf->frame_max : 1.0;
     const double dq = rf->dtype == HODMAS_I16 ? (double)rf->dequant_scale : 1.0;
     p->in_scale = (float)(dq / fm);
@@ -393,7 +418,8 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
     const FrameArgs a = hodmas::frame_args(plan, rf_dev, image_dev);
     const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
     const bool cf = (plan->flags & HODMAS_FLAG_CF) != 0;
-    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, cf, plan->lds_bytes, stream);
+    const bool mirror = (plan->flags & HODMAS_FLAG_MIRROR) != 0;
+    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, cf, mirror, plan->lds_bytes, stream);
     if (cur != plan->device)
         (void)hipSetDevice(cur);
     return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;

@@ -66,8 +66,10 @@ struct BatchUnit {
 };
 
 // Launch one frame on `stream`.  Returns hipSuccess or the launch error code.
+// mirror: pair each tile of the grid's left half with its mirror image (grid
+// n_tiles / 2); the plan has checked that the geometry allows it.
 int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, bool coherence,
-                 int64_t lds_bytes, void* stream);
+                 bool mirror, int64_t lds_bytes, void* stream);
 
 constexpr uint32_t kPlanMagic = 0x484f444du;  // "HODM"
 

@@ -176,27 +176,35 @@ __device__ __forceinline__ void terms(float v, float (&T)[n_sums<K, CF>()])
     }
 }
 
-template <int DT>
+// Rows [0, nch) of the LDS receive the chunk's slots (row r: slot r's element
+// over its sample window).  With M == 2 (mirror pairing) rows [nch, 2 nch)
+// receive the mirrored elements, n_elements - 1 - element, over the same
+// sample windows: the mirror pixel reads them at the same delays.
+template <int DT, int M>
 __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, int nch, int window,
                                             float* __restrict__ lds, int wave, int nwaves, int lane)
 {
     using T = typename Storage<DT>::T;
     const Global<const T> rf = global_ptr(static_cast<const T*>(A.rf));
-    // Each wave stages a contiguous run of slots; lanes run along the window.
+    // Each wave stages a contiguous run of rows; lanes run along the window.
     // Latency, not bandwidth, sets the cost here: one vector load brings 64
-    // slots' table entries (lane j holds slot j), then the sample loads go out
+    // rows' table entries (lane j holds row j), then the sample loads go out
     // kInFlight at a time before any wait, their addresses read out of the
-    // entry lanes.  Every load address is clamped in bounds (slot to the
+    // entry lanes.  Every load address is clamped in bounds (row to the
     // chunk, sample to the record); out-of-range lanes store zero.
     constexpr int kInFlight = 16;
-    const int per_wave = (nch + nwaves - 1) / nwaves;
+    const int rows = M * nch;
+    const int per_wave = (rows + nwaves - 1) / nwaves;
     const int s0 = wave * per_wave;
-    const int s1 = min(nch, s0 + per_wave);
+    const int s1 = min(rows, s0 + per_wave);
     const Global<const int> ent = global_ptr(reinterpret_cast<const int*>(st));
     for (int c = s0; c < s1; c += 64) {
         const int j = min(c + lane, s1 - 1);
-        const int my_channel = ent[2 * j];
-        const int my_first = ent[2 * j + 1];
+        const bool mirrored = M == 2 && j >= nch;
+        const int src = mirrored ? j - nch : j;
+        const int elem = ent[2 * src];
+        const int my_channel = mirrored ? A.n_elements - 1 - elem : elem;
+        const int my_first = ent[2 * src + 1];
         const int cend = min(s1 - c, 64);
         for (int base = 0; base < window; base += 64) {
             const int i = base + lane;
@@ -256,64 +264,86 @@ __device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[
 // in -- the scalar loads of the next group's constants (the LDS/scalar wait
 // counter does not order scalar loads, so issuing them earlier would make
 // this group's waits also wait for them), then roots, powers and the sums.
-template <int K, bool CF, bool COMP, bool CHECK, int NS = n_sums<K, CF>()>
+// With M == 2 each delay also serves the lane's mirror pixel, whose samples
+// sit `moff` bytes further on in the LDS (the mirrored rows).
+template <int K, bool CF, bool COMP, bool CHECK, int M, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], float u2, float q,
-                                              const float* __restrict__ lds, float (&s)[NS], float (&P)[NS],
-                                              bool more, ConstEntry En, hodmas_chan_entry (&en)[4])
+                                              const float* __restrict__ lds, int moff, float (&s)[M][NS],
+                                              float (&P)[M][NS], bool more, ConstEntry En,
+                                              hodmas_chan_entry (&en)[4])
 {
     Tap tp[4];
-    float s0[4], s1[4], v[4];
+    float s0[M][4], s1[M][4], v[M][4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         tp[m] = locate(e[m], u2, q);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        s0[m] = lds_at(lds, tp[m].addr);
-        s1[m] = lds_at(lds, tp[m].addr + 4);
+    for (int mm = 0; mm < M; ++mm) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            s0[mm][m] = lds_at(lds, tp[m].addr + mm * moff);
+            s1[mm][m] = lds_at(lds, tp[m].addr + mm * moff + 4);
+        }
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        v[m] = interp<CHECK>(tp[m], e[m], s0[m], s1[m]);
-    // emits nothing: makes the four samples (hence this group's LDS waits)
+    for (int mm = 0; mm < M; ++mm) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            v[mm][m] = interp<CHECK>(tp[m], e[m], s0[mm][m], s1[mm][m]);
+    }
+    // emits nothing: makes the samples (hence this group's LDS waits)
     // complete before the scalar loads below are issued
-    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]) : "memory");
+#pragma unroll
+    for (int mm = 0; mm < M; ++mm)
+        asm volatile("" ::"v"(v[mm][0]), "v"(v[mm][1]), "v"(v[mm][2]), "v"(v[mm][3]) : "memory");
     if (more)
         load_group(En, en);
-    float T[4][NS];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        terms<K, CF>(v[m], T[m]);
+    for (int mm = 0; mm < M; ++mm) {
+        float T[4][NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        if (COMP) {
-            P[j] += (T[0][j] + T[1][j]) + (T[2][j] + T[3][j]);
-        } else {
-            s[j] += T[0][j];
-            s[j] += T[1][j];
-            s[j] += T[2][j];
-            s[j] += T[3][j];
+        for (int m = 0; m < 4; ++m)
+            terms<K, CF>(v[mm][m], T[m]);
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            if (COMP) {
+                P[mm][j] += (T[0][j] + T[1][j]) + (T[2][j] + T[3][j]);
+            } else {
+                s[mm][j] += T[0][j];
+                s[mm][j] += T[1][j];
+                s[mm][j] += T[2][j];
+                s[mm][j] += T[3][j];
+            }
         }
     }
 }
 
-template <int K, bool COMP>
-__device__ __forceinline__ void after_group(int& groups, float (&s)[K], float (&c)[K], float (&P)[K])
+template <int NS, bool COMP, int M>
+__device__ __forceinline__ void after_group(int& groups, float (&s)[M][NS], float (&c)[M][NS],
+                                            float (&P)[M][NS])
 {
-    if (COMP && (++groups & 3) == 0)
-        flush<K>(s, c, P);
+    if (COMP && (++groups & 3) == 0) {
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm)
+            flush<NS>(s[mm], c[mm], P[mm]);
+    }
 }
 
 // The n elements of this wave's split group in one staged chunk (their
 // constants stored contiguously), four at a time; two constant sets alternate
 // so nothing is copied between them.
-template <int K, bool CF, bool COMP, bool CHECK, int NS = n_sums<K, CF>()>
+template <int K, bool CF, bool COMP, bool CHECK, int M, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, float q,
-                                                 const float* __restrict__ lds, float (&s)[NS], float (&c)[NS])
+                                                 const float* __restrict__ lds, int moff, float (&s)[M][NS],
+                                                 float (&c)[M][NS])
 {
-    float P[NS];
+    float P[M][NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j)
-        P[j] = 0.f;
+    for (int mm = 0; mm < M; ++mm) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
+            P[mm][j] = 0.f;
+    }
     int sl = 0;
     if (n >= 4) {
         hodmas_chan_entry ea[4], eb[4];
@@ -321,14 +351,14 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
-            after_group<NS, COMP>(groups, s, c, P);
+            process_group<K, CF, COMP, CHECK, M>(ea, u2, q, lds, moff, s, P, more_a, E + sl + 4, eb);
+            after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
-            after_group<NS, COMP>(groups, s, c, P);
+            process_group<K, CF, COMP, CHECK, M>(eb, u2, q, lds, moff, s, P, more_b, E + sl + 4, ea);
+            after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_b)
                 break;
@@ -337,18 +367,25 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
     for (; sl < n; ++sl) {
         const hodmas_chan_entry e = load_const(E, sl);
         const Tap tp = locate(e, u2, q);
-        float T[NS];
-        terms<K, CF>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
 #pragma unroll
-        for (int j = 0; j < NS; ++j) {
-            if (COMP)
-                P[j] += T[j];
-            else
-                s[j] += T[j];
+        for (int mm = 0; mm < M; ++mm) {
+            float T[NS];
+            const int addr = tp.addr + mm * moff;
+            terms<K, CF>(interp<CHECK>(tp, e, lds_at(lds, addr), lds_at(lds, addr + 4)), T);
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                if (COMP)
+                    P[mm][j] += T[j];
+                else
+                    s[mm][j] += T[j];
+            }
         }
     }
-    if (COMP)
-        flush<NS>(s, c, P);
+    if (COMP) {
+#pragma unroll
+        for (int mm = 0; mm < M; ++mm)
+            flush<NS>(s[mm], c[mm], P[mm]);
+    }
 }
 
 // Newton's identities: e_m = (1/m) sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
@@ -373,7 +410,12 @@ __device__ __forceinline__ R newton(const R (&p)[K])
 // One pixel tile of one frame: stage, accumulate, combine, recover, store.
 // Every thread of the workgroup calls this with the same (A, tile); all
 // branches on tile data are workgroup-uniform, so the barriers inside match.
-template <int K, int DT, bool COMP, bool CF = false>
+// With M == 2 the workgroup also forms the mirror tile: the pixel at column
+// nx-1-ix of each lane's own pixel at ix.  When the array and the grid are
+// symmetric about x = 0 (checked on the host), that pixel's delay to element
+// n-1-i equals this pixel's delay to element i, so one delay serves both and
+// the mirror pixel gathers from the mirrored rows the staging fills.
+template <int K, int DT, bool COMP, bool CF = false, int M = 1>
 __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
 {
     constexpr int NS = n_sums<K, CF>();
@@ -389,12 +431,18 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     const bool valid = lx < td.nx && lz < td.nz;
     const int ix = td.ix0 + min(lx, td.nx - 1);
     const int iz = td.iz0 + min(lz, td.nz - 1);
-    const Global<float> dst = global_ptr(A.image + (int64_t)iz * A.nx + ix);
+    Global<float> dst[M];
+    dst[0] = global_ptr(A.image + (int64_t)iz * A.nx + ix);
+    if constexpr (M == 2)
+        dst[1] = global_ptr(A.image + (int64_t)iz * A.nx + (A.nx - 1 - ix));
 
     if (td.n_active < K) {
         // fewer contributing elements than the order: no K-subset exists, e_K = 0 exactly
-        if (g == 0 && valid)
-            *dst = 0.f;
+        if (g == 0 && valid) {
+#pragma unroll
+            for (int mm = 0; mm < M; ++mm)
+                *dst[mm] = 0.f;
+        }
         return;
     }
 
@@ -404,53 +452,64 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     const float u2 = (float)(2.0 * u);
     const float q = (float)(u * u + w * (w + 2.0 * td.za));
 
-    float s[NS], c[NS];
+    float s[M][NS], c[M][NS];
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        s[j] = 0.f;
-        c[j] = 0.f;
+    for (int mm = 0; mm < M; ++mm) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            s[mm][j] = 0.f;
+            c[mm][j] = 0.f;
+        }
     }
     ConstEntry E = A.entries + td.first_entry;
     ConstStage St = A.stage + td.first_entry;
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();                       // previous readers of the LDS are done
-        stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        stage_chunk<DT, M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
+        const int moff = nch * td.window * 4;  // bytes from a slot's row to its mirrored row
         // this group's elements of the chunk: slots g, g+split, ..., stored together
         int goff = 0;
         for (int h = 0; h < g; ++h)
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
         if (td.check)
-            accumulate_chunk<K, CF, COMP, true>(E + c0 + goff, ng, u2, q, lds, s, c);
+            accumulate_chunk<K, CF, COMP, true, M>(E + c0 + goff, ng, u2, q, lds, moff, s, c);
         else
-            accumulate_chunk<K, CF, COMP, false>(E + c0 + goff, ng, u2, q, lds, s, c);
+            accumulate_chunk<K, CF, COMP, false, M>(E + c0 + goff, ng, u2, q, lds, moff, s, c);
     }
 
     if (A.split > 1) {
         // fixed-order combination of the groups' partial sums through LDS
+        constexpr int W = 2 * M * NS;          // floats per pixel and group
         __syncthreads();
         float* red = lds;
         if (g > 0) {
 #pragma unroll
-            for (int j = 0; j < NS; ++j) {
-                red[((g - 1) * npix + pl) * 2 * NS + 2 * j] = s[j];
-                red[((g - 1) * npix + pl) * 2 * NS + 2 * j + 1] = c[j];
+            for (int mm = 0; mm < M; ++mm) {
+#pragma unroll
+                for (int j = 0; j < NS; ++j) {
+                    red[((g - 1) * npix + pl) * W + 2 * (mm * NS + j)] = s[mm][j];
+                    red[((g - 1) * npix + pl) * W + 2 * (mm * NS + j) + 1] = c[mm][j];
+                }
             }
         }
         __syncthreads();
         if (g == 0) {
             for (int gg = 1; gg < A.split; ++gg) {
 #pragma unroll
-                for (int j = 0; j < NS; ++j) {
-                    const float so = red[((gg - 1) * npix + pl) * 2 * NS + 2 * j];
-                    const float co = red[((gg - 1) * npix + pl) * 2 * NS + 2 * j + 1];
-                    if (COMP) {
-                        kahan_add(s[j], c[j], so);
-                        kahan_add(s[j], c[j], -co);
-                    } else {
-                        s[j] += so;
+                for (int mm = 0; mm < M; ++mm) {
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) {
+                        const float so = red[((gg - 1) * npix + pl) * W + 2 * (mm * NS + j)];
+                        const float co = red[((gg - 1) * npix + pl) * W + 2 * (mm * NS + j) + 1];
+                        if (COMP) {
+                            kahan_add(s[mm][j], c[mm][j], so);
+                            kahan_add(s[mm][j], c[mm][j], -co);
+                        } else {
+                            s[mm][j] += so;
+                        }
                     }
                 }
             }
@@ -459,27 +518,40 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     if (g != 0 || !valid)
         return;
     using R = typename std::conditional<(K >= 5), double, float>::type;
-    R p[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j)
-        p[j] = COMP ? R(s[j]) - R(c[j]) : R(s[j]);
-    const R ek = newton<K, R>(p);
-    if constexpr (CF) {
-        // coherence factor (sum v)^2 / (N sum v^2) of the normalised samples
-        const double s1 = COMP ? double(s[K]) - double(c[K]) : double(s[K]);
-        const double s2 = COMP ? double(s[K + 1]) - double(c[K + 1]) : double(s[K + 1]);
-        const double cf = s2 > 0.0 ? (s1 * s1) / (double(A.n_elements) * s2) : 0.0;
-        *dst = (float)(double(ek) * cf * double(A.out_scale));
-    } else {
-        *dst = (float)(ek * R(A.out_scale));
+    for (int mm = 0; mm < M; ++mm) {
+        R p[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            p[j] = COMP ? R(s[mm][j]) - R(c[mm][j]) : R(s[mm][j]);
+        const R ek = newton<K, R>(p);
+        if constexpr (CF) {
+            // coherence factor (sum v)^2 / (N sum v^2) of the normalised samples
+            const double s1 = COMP ? double(s[mm][K]) - double(c[mm][K]) : double(s[mm][K]);
+            const double s2 = COMP ? double(s[mm][K + 1]) - double(c[mm][K + 1]) : double(s[mm][K + 1]);
+            const double cf = s2 > 0.0 ? (s1 * s1) / (double(A.n_elements) * s2) : 0.0;
+            *dst[mm] = (float)(double(ek) * cf * double(A.out_scale));
+        } else {
+            *dst[mm] = (float)(ek * R(A.out_scale));
+        }
     }
 }
 
-template <int K, int DT, bool COMP, bool CF>
+// M == 1: workgroup b forms tile xcd_tile(b).  M == 2: workgroup b forms pair
+// p = xcd_tile(b) of the n_tiles / 2 pairs -- the p-th tile of the grid's
+// left half (row-major over its tile rows) and that tile's mirror image.
+template <int K, int DT, bool COMP, bool CF, int M>
 __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 {
     extern __shared__ float lds[];
-    process_tile<K, DT, COMP, CF>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
+    if constexpr (M == 1) {
+        process_tile<K, DT, COMP, CF, 1>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
+    } else {
+        const int half = A.nx / A.tile_x / 2;     // tile columns left of the centre
+        const int p = xcd_tile(blockIdx.x, A.n_tiles / 2);
+        const int bz = p / half;
+        process_tile<K, DT, COMP, CF, 2>(A, bz * 2 * half + (p - bz * half), lds);
+    }
 }
 
 // Persistent form: one kernel per (order, storage type).  Its fixed grid walks
@@ -742,7 +814,7 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();
-        stage_chunk<DT>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        stage_chunk<DT, 1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
         int goff = 0;
         for (int h = 0; h < g; ++h)
@@ -822,31 +894,48 @@ int launch_orders_dt(const FrameArgs& a, const OrderImages& out, int kmax, bool 
     return (int)hipErrorInvalidValue;
 }
 
-template <int K, int DT>
-int launch_k(const FrameArgs& a, bool comp, bool cf, int64_t lds_bytes, hipStream_t st)
+// A workgroup may hold more than 64 KB of LDS only once the kernel says so.
+int launch_one(void (*fn)(FrameArgs), dim3 grid, dim3 block, int64_t lds_bytes, hipStream_t st,
+               const FrameArgs& a)
 {
-    dim3 grid(a.n_tiles), block(a.block);
-    if (comp && cf)
-        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true, true>), grid, block, (size_t)lds_bytes, st, a);
-    else if (comp)
-        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, true, false>), grid, block, (size_t)lds_bytes, st, a);
-    else if (cf)
-        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, false, true>), grid, block, (size_t)lds_bytes, st, a);
-    else
-        hipLaunchKernelGGL((hodmas_frame_kernel<K, DT, false, false>), grid, block, (size_t)lds_bytes, st, a);
+    if (lds_bytes > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes) != hipSuccess)
+        return (int)hipGetLastError();
+    hipLaunchKernelGGL(fn, grid, block, (size_t)lds_bytes, st, a);
     return (int)hipGetLastError();
 }
 
+template <int K, int DT, int M>
+int launch_km(const FrameArgs& a, bool comp, bool cf, int64_t lds_bytes, hipStream_t st)
+{
+    const dim3 grid(a.n_tiles / M), block(a.block);
+    if (comp && cf)
+        return launch_one(hodmas_frame_kernel<K, DT, true, true, M>, grid, block, lds_bytes, st, a);
+    if (comp)
+        return launch_one(hodmas_frame_kernel<K, DT, true, false, M>, grid, block, lds_bytes, st, a);
+    if (cf)
+        return launch_one(hodmas_frame_kernel<K, DT, false, true, M>, grid, block, lds_bytes, st, a);
+    return launch_one(hodmas_frame_kernel<K, DT, false, false, M>, grid, block, lds_bytes, st, a);
+}
+
+template <int K, int DT>
+int launch_k(const FrameArgs& a, bool comp, bool cf, bool mirror, int64_t lds_bytes, hipStream_t st)
+{
+    return mirror ? launch_km<K, DT, 2>(a, comp, cf, lds_bytes, st) : launch_km<K, DT, 1>(a, comp, cf, lds_bytes, st);
+}
+
 template <int DT>
-int launch_dt(const FrameArgs& a, int order, bool comp, bool cf, int64_t lds_bytes, hipStream_t st)
+int launch_dt(const FrameArgs& a, int order, bool comp, bool cf, bool mirror, int64_t lds_bytes,
+              hipStream_t st)
 {
     switch (order) {
-    case 1: return launch_k<1, DT>(a, comp, cf, lds_bytes, st);
-    case 2: return launch_k<2, DT>(a, comp, cf, lds_bytes, st);
-    case 3: return launch_k<3, DT>(a, comp, cf, lds_bytes, st);
-    case 4: return launch_k<4, DT>(a, comp, cf, lds_bytes, st);
-    case 5: return launch_k<5, DT>(a, comp, cf, lds_bytes, st);
-    case 6: return launch_k<6, DT>(a, comp, cf, lds_bytes, st);
+    case 1: return launch_k<1, DT>(a, comp, cf, mirror, lds_bytes, st);
+    case 2: return launch_k<2, DT>(a, comp, cf, mirror, lds_bytes, st);
+    case 3: return launch_k<3, DT>(a, comp, cf, mirror, lds_bytes, st);
+    case 4: return launch_k<4, DT>(a, comp, cf, mirror, lds_bytes, st);
+    case 5: return launch_k<5, DT>(a, comp, cf, mirror, lds_bytes, st);
+    case 6: return launch_k<6, DT>(a, comp, cf, mirror, lds_bytes, st);
     }
     return (int)hipErrorInvalidValue;
 }
@@ -854,13 +943,13 @@ int launch_dt(const FrameArgs& a, int order, bool comp, bool cf, int64_t lds_byt
 }  // namespace
 
 int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, bool coherence,
-                 int64_t lds_bytes, void* stream)
+                 bool mirror, int64_t lds_bytes, void* stream)
 {
     hipStream_t st = static_cast<hipStream_t>(stream);
     switch (dtype) {
-    case HODMAS_F32: return launch_dt<HODMAS_F32>(a, order, compensated, coherence, lds_bytes, st);
-    case HODMAS_F16: return launch_dt<HODMAS_F16>(a, order, compensated, coherence, lds_bytes, st);
-    case HODMAS_I16: return launch_dt<HODMAS_I16>(a, order, compensated, coherence, lds_bytes, st);
+    case HODMAS_F32: return launch_dt<HODMAS_F32>(a, order, compensated, coherence, mirror, lds_bytes, st);
+    case HODMAS_F16: return launch_dt<HODMAS_F16>(a, order, compensated, coherence, mirror, lds_bytes, st);
+    case HODMAS_I16: return launch_dt<HODMAS_I16>(a, order, compensated, coherence, mirror, lds_bytes, st);
     }
     return (int)hipErrorInvalidValue;
 }

@@ -32,7 +32,8 @@ std::string tune_key(const char* arch, const hodmas_geometry* g, const hodmas_gr
                   arch, g->n_elements, g->pitch_m, g->sound_speed_m_s, g->fs_hz, g->t0_s, h, gr->nx,
                   gr->nz, gr->x0_m, gr->dx_m, gr->z0_m, gr->dz_m, rf->dtype, rf->n_samples,
                   (long long)rf->channel_stride, order,
-                  (unsigned)(flags & (HODMAS_FLAG_ACC_PLAIN | HODMAS_FLAG_TUNE_BATCH | HODMAS_FLAG_CF)));
+                  (unsigned)(flags & (HODMAS_FLAG_ACC_PLAIN | HODMAS_FLAG_TUNE_BATCH | HODMAS_FLAG_CF |
+                                      HODMAS_FLAG_MIRROR)));
     return buf;
 }
 

@@ -1,0 +1,168 @@
+"""Mirror pairing (HODMAS_FLAG_MIRROR): one workgroup forms a tile and its
+mirror image about x = 0 from one set of delays.  Images are checked against
+the FP64 oracle to the same bars as the unpaired kernel (relative L2 1e-5 for
+FP32 storage, 2e-5 on the same stored values for FP16 / int16) and against the
+unpaired launch (rounding-level differences only), over ragged grids, several
+tilings, multi-chunk staging, record-boundary checks, coherence weighting and
+odd and even element counts."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2203_14906_amd import phantom as ph
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f16": 2e-5, "i16": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def hd():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2203_14906_amd import hodmas
+    return hodmas
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(g, o):
+    n = np.linalg.norm(o)
+    return np.linalg.norm(g - o) / n if n > 0 else np.linalg.norm(g)
+
+
+def stored(rf, dtype, seed=0):
+    if dtype == "f32":
+        return ph.to_fp32(rf), 1.0
+    if dtype == "f16":
+        return ph.to_fp16(rf), 1.0
+    codes, scale = ph.to_int16(rf, seed)
+    return codes, float(scale)
+
+
+def symmetric_grid(nx, nz, dx, z0, dz):
+    return ph.Grid(nx=nx, nz=nz, x0_m=-(nx - 1) / 2.0 * dx, dx_m=dx, z0_m=z0, dz_m=dz)
+
+
+@pytest.mark.parametrize("n_elem", [13, 16])
+@pytest.mark.parametrize("tiling", [None, (16, 16, 1, 64), (16, 8, 2, 5), (8, 8, 4, 3), (16, 16, 2, 0)])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "i16"])
+def test_mirror_small_ragged_frames(hd, n_elem, tiling, dtype):
+    f = ph.make_frame(n_elem, 300, 64, 53, n_points=6, n_lines=1, snr_db=15.0, seed=21)
+    grid = symmetric_grid(64, 53, 0.17e-3, 0.2e-3, 0.21e-3)
+    arr, scale = stored(f.rf, dtype, seed=21)
+    kw = dict(max_order=6, dequant_scale=scale, tiling=tiling)
+    plan = hd.Plan(f.geometry, grid, arr.shape[1], dtype, flags=hd.FLAG_MIRROR, **kw)
+    ref = hd.Plan(f.geometry, grid, arr.shape[1], dtype, **kw)
+    dev = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    say("mirror small n=%d %s %s chunk %d" % (n_elem, dtype, tiling, plan.info().tiling.chunk))
+    for k in range(1, 7):
+        g = plan.beamform(dev, k).cpu().numpy().astype(np.float64)
+        u = ref.beamform(dev, k).cpu().numpy().astype(np.float64)
+        o = O.beamform(arr, f.geometry, grid, k, dequant_scale=scale if dtype == "i16" else None)
+        err, err_u = rel_l2(g, o), rel_l2(g, u)
+        say("  k=%d rel L2 vs oracle %.2e, vs unpaired %.2e" % (k, err, err_u))
+        assert err <= TOL[dtype]
+        assert err_u <= TOL[dtype]
+    plan.close()
+    ref.close()
+
+
+def test_mirror_record_checks_and_skipped_elements(hd):
+    """Deep pixels run past the record (per-sample checks, elements left out of
+    tiles); FORCE_CHECK runs the checks everywhere."""
+    S = 330
+    f = ph.make_frame(24, S, 64, 45, n_points=8, n_lines=1, snr_db=20.0, seed=5)
+    grid = ph.make_grid(64, 45, 24 * 0.3e-3 * 1.5, 14e-3)
+    arr = ph.to_fp32(f.rf)
+    dev = torch.from_numpy(arr).cuda()
+    for flags in (hd.FLAG_MIRROR, hd.FLAG_MIRROR | hd.FLAG_FORCE_CHECK, hd.FLAG_MIRROR | hd.FLAG_ACC_PLAIN):
+        for tiling in ((16, 16, 1, 8), (8, 8, 4, 3)):
+            plan = hd.Plan(f.geometry, grid, S, "f32", max_order=6, tiling=tiling, flags=flags)
+            for k in (1, 2, 4, 6):
+                g = plan.beamform(dev, k).cpu().numpy().astype(np.float64)
+                o = O.beamform(arr, f.geometry, grid, k)
+                err = rel_l2(g, o)
+                say("mirror deep flags %d %s k=%d rel L2 %.2e" % (flags, tiling, k, err))
+                assert err <= 1e-5
+            plan.close()
+
+
+@pytest.mark.parametrize("cfg,orders", [(1, (1, 2, 3, 4)), (2, (1, 2, 3, 4, 5, 6))])
+def test_mirror_configs(hd, cfg, orders):
+    f = ph.config_frame(cfg)
+    arr = ph.to_fp32(f.rf)
+    dev = torch.from_numpy(arr).cuda()
+    for tiling in (None, (16, 8, 2, 0)):
+        plan = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, tiling=tiling,
+                       flags=hd.FLAG_MIRROR)
+        for k in orders:
+            g = plan.beamform(dev, k).cpu().numpy().astype(np.float64)
+            o = O.beamform(arr, f.geometry, f.grid, k)
+            err = rel_l2(g, o)
+            say("mirror config %d %s k=%d rel L2 %.2e" % (cfg, tiling, k, err))
+            assert err <= 1e-5
+        plan.close()
+
+
+def test_mirror_with_coherence_factor(hd):
+    f = ph.make_frame(16, 300, 64, 53, n_points=6, n_lines=1, snr_db=15.0, seed=9)
+    grid = symmetric_grid(64, 53, 0.17e-3, 0.2e-3, 0.21e-3)
+    arr = ph.to_fp32(f.rf)
+    dev = torch.from_numpy(arr).cuda()
+    for tiling in (None, (8, 8, 4, 3)):
+        plan = hd.Plan(f.geometry, grid, 300, "f32", max_order=6, tiling=tiling,
+                       flags=hd.FLAG_MIRROR | hd.FLAG_CF)
+        for k in (1, 2, 3, 6):
+            g = plan.beamform(dev, k).cpu().numpy().astype(np.float64)
+            o = O.beamform(arr, f.geometry, grid, k, weighting="cf")
+            err = rel_l2(g, o)
+            say("mirror CF %s k=%d rel L2 %.2e" % (tiling, k, err))
+            assert err <= 1e-5
+        plan.close()
+
+
+def test_mirror_symmetric_input_gives_symmetric_image(hd):
+    """Channel records mirrored about the array centre make a mirror-symmetric
+    image; the paired kernel forms both halves from the same delays."""
+    f = ph.make_frame(32, 512, 64, 64, n_points=6, n_lines=0, snr_db=30.0, seed=2)
+    rf = 0.5 * (f.rf + f.rf[::-1])
+    arr = ph.to_fp32(rf)
+    grid = symmetric_grid(64, 64, 0.15e-3, 1e-3, 0.15e-3)
+    plan = hd.Plan(f.geometry, grid, 512, "f32", max_order=6, flags=hd.FLAG_MIRROR)
+    dev = torch.from_numpy(arr).cuda()
+    for k in (1, 3, 6):
+        g = plan.beamform(dev, k).cpu().numpy()
+        say("mirror symmetry k=%d max |left - right| %.3g" % (k, np.abs(g - g[:, ::-1]).max()))
+        # the mirrored rows hold the same samples, read at the same delays,
+        # summed in the same order: the halves agree bit for bit
+        assert np.array_equal(g, g[:, ::-1])
+    plan.close()
+
+
+def test_mirror_plan_in_other_entry_points(hd):
+    """The all-orders pass runs a mirror plan unpaired (same images); the batch
+    refuses it."""
+    f = ph.config_frame(1)
+    arr = ph.to_fp32(f.rf)
+    dev = torch.from_numpy(arr).cuda()
+    plan = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=4, flags=hd.FLAG_MIRROR)
+    imgs = plan.beamform_orders(dev, 4)
+    for k in range(1, 5):
+        o = O.beamform(arr, f.geometry, f.grid, k)
+        err = rel_l2(imgs[k - 1].cpu().numpy().astype(np.float64), o)
+        say("mirror plan, all-orders pass k=%d rel L2 %.2e" % (k, err))
+        assert err <= 1e-5
+    info = plan.info()
+    bt = hd.Batch(max_frames=1, max_units=info.n_tiles, max_lds_bytes=64 * 1024)
+    out = torch.empty((f.grid.nz, f.grid.nx), dtype=torch.float32, device="cuda")
+    with pytest.raises(hd.HodmasError) as ei:
+        bt.set([plan], [dev], [1], [out])
+    assert ei.value.status == hd.EINVAL
+    bt.close()
+    plan.close()

@@ -207,3 +207,99 @@ def test_autotune_argument_validation_without_device():
     assert L.hodmas_autotune(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), 1, hodmas.FLAG_HOST_ONLY, None,
                              ctypes.byref(t)) == hodmas.EINVAL
     assert L.hodmas_autotune(ctypes.byref(g), ctypes.byref(gr), ctypes.byref(rd), 1, 0, None, None) == hodmas.EINVAL
+
+
+def test_mirror_validation_and_default_tiling():
+    M, E = hodmas.FLAG_MIRROR, hodmas.EINVAL
+    g = ph.Geometry(24)
+    grid = ph.make_grid(64, 40, 24 * 0.3e-3, 10e-3)
+    p = _plan(g, grid, 512, flags=M)
+    inf = p.info()
+    assert inf.flags & M
+    assert inf.tiling.tile_x == 16 and (64 // 16) % 2 == 0
+    p.close()
+    # 48 columns: 16-wide tiles would give an odd count, so the default is 8 wide
+    p = _plan(g, ph.make_grid(48, 40, 24 * 0.3e-3, 10e-3), 512, flags=M)
+    assert p.info().tiling.tile_x == 8
+    p.close()
+    # a grid off centre by a tenth of a pixel, a shifted or uneven array, tiles
+    # that do not divide the grid or give an odd column count: refused
+    off = ph.Grid(64, 40, grid.x0_m + 0.1 * grid.dx_m, grid.dx_m, grid.z0_m, grid.dz_m)
+    assert _status(lambda: _plan(g, off, 512, flags=M)) == E
+    ex = g.positions()
+    assert _status(lambda: _plan(ph.Geometry(24, element_x_m=ex + 1e-5), grid, 512, flags=M)) == E
+    bent = ex.copy()
+    bent[3] += 1e-5
+    assert _status(lambda: _plan(ph.Geometry(24, element_x_m=bent), grid, 512, flags=M)) == E
+    assert _status(lambda: _plan(g, ph.make_grid(60, 40, 24 * 0.3e-3, 10e-3), 512, flags=M,
+                                 tiling=(16, 16, 1, 0))) == E     # 16 does not divide 60
+    assert _status(lambda: _plan(g, ph.make_grid(48, 40, 24 * 0.3e-3, 10e-3), 512, flags=M,
+                                 tiling=(16, 16, 1, 0))) == E     # three columns
+    # an explicitly symmetric array given element by element is accepted
+    _plan(ph.Geometry(24, element_x_m=ex), grid, 512, flags=M).close()
+
+
+def test_mirror_lds_holds_both_rows():
+    f = ph.config_frame(2)
+    plain = _plan(f.geometry, f.grid, 2048)
+    mir = _plan(f.geometry, f.grid, 2048, flags=hodmas.FLAG_MIRROR)
+    a, b = plain.info(), mir.info()
+    assert b.max_window == a.max_window
+    assert b.lds_bytes == 2 * b.tiling.chunk * b.max_window * 4 <= 40 * 1024
+    assert b.tiling.chunk <= a.tiling.chunk
+    plain.close()
+    mir.close()
+
+
+@pytest.mark.parametrize("n_elem,tiling", [(24, (16, 16, 1, 8)), (13, (8, 8, 4, 3)), (32, (16, 8, 2, 0))])
+def test_mirror_pixels_read_the_mirrored_delays(n_elem, tiling):
+    """Each lane forms its pixel P from its tile's constants and, with the same
+    float32 delay, the mirror pixel P' at element n-1-i from the mirrored LDS
+    row.  Check on the host that this delay is P''s own delay to the mirrored
+    element, that the mirrored row's sample window covers it, and that an
+    element the tile skips contributes nothing to P' either."""
+    S = 330                                                        # deep pixels run past the record
+    g = ph.Geometry(n_elem)
+    grid = ph.make_grid(64, 45, n_elem * 0.3e-3 * 1.5, 14e-3)       # wider than the array, ragged in z
+    plan = _plan(g, grid, S, tiling=tiling, flags=hodmas.FLAG_MIRROR)
+    info = plan.info()
+    tiles, entries, stage = plan.tables()
+    ex = g.positions()
+    n = len(ex)
+    tx = info.tiling.tile_x
+    ntx = grid.nx // tx
+    n_checked = n_skipped = 0
+    for td in tiles:
+        if td.ix0 // tx >= ntx // 2:
+            continue                                               # right half: formed as mirrors
+        assert td.nx == tx
+        ixs, izs = np.meshgrid(np.arange(td.ix0, td.ix0 + td.nx), np.arange(td.iz0, td.iz0 + td.nz))
+        ixs, izs = ixs.ravel(), izs.ravel()
+        tm = _exact_delays(ex, grid, 0.0, grid.nx - 1 - ixs, izs)   # mirror pixels, every element
+        u = (grid.x0_m + ixs * grid.dx_m) / LAM - td.xa
+        w = (grid.z0_m + izs * grid.dz_m) / LAM - td.za
+        u2 = (2.0 * u).astype(np.float32)
+        q = (u * u + w * (w + 2.0 * td.za)).astype(np.float32)
+        active = {st.channel for st in stage[td.first_entry:td.first_entry + td.n_active]}
+        for i in range(n):
+            if i not in active:
+                assert np.all((tm[:, n - 1 - i] < 0) | (tm[:, n - 1 - i] > S - 1))
+        by_elem = {e.channel: e for e in entries[td.first_entry:td.first_entry + td.n_active]}
+        for slot in range(td.n_active):
+            st = stage[td.first_entry + slot]
+            e = by_elem[st.channel]
+            T0 = int(round(-e.lo))
+            num = (u2.astype(np.float64) * np.float64(e.a) + q).astype(np.float32)
+            d = np.sqrt(np.abs(np.float64(e.d0sq) + num)).astype(np.float32)
+            r = (1.0 / (d.astype(np.float64) + np.float64(e.d0))).astype(np.float32)
+            trel = (num.astype(np.float64) * r + np.float64(e.frac0)).astype(np.float32)
+            exact = tm[:, n - 1 - st.channel] - T0
+            assert np.max(np.abs(trel - exact)) < 1e-3
+            if not td.check:
+                j = np.floor(trel).astype(np.int64) + T0 - st.first_sample
+                assert j.min() >= 0 and j.max() + 1 <= td.window - 1
+            n_checked += int(td.check)
+            n_skipped += n - td.n_active
+    assert n_checked > 0                                           # tiles at the record's end
+    assert n_skipped > 0 or n_elem == 24                           # elements left out of tiles
+    plan.close()
