@@ -9,7 +9,9 @@ over the orders, with the per-order rates beside it.
 
 Prints ONE JSON line.  Also reports:
   roofline      the dominant kernel (the order with the most device time) against
-                the VALU issue peak, from HIP events on the launch stream;
+                the published FP32 vector peak, from HIP events on the launch
+                stream, and every order against the ceiling set by this
+                device's measured unpacked-FP32 and transcendental issue rates;
   cpu_baseline  the FP64 oracle timed on this host on the same batch.
 """
 import argparse
@@ -32,6 +34,11 @@ SLOTS = {1: 19, 2: 25, 3: 32, 4: 32, 5: 36, 6: 38}
 # 157.3 TFLOP/s FP32 vector (published) = 78.6e12 FMA lane-slots/s
 # (256 CUs x 128 FP32 lanes/clock x 2.4 GHz).
 VALU_PEAK_TSLOT = 78.64
+# The same work split into plain FP32 operations and transcendentals (SLOTS =
+# NONTRANS + 4 TRANS): the ceiling against the device's measured issue rates
+# is 1 / (NONTRANS / R_fp32 + TRANS / R_trans) pixel-channels per second.
+NONTRANS = {1: 11, 2: 13, 3: 16, 4: 16, 5: 20, 6: 22}
+TRANS = {1: 2, 2: 3, 3: 4, 4: 4, 5: 4, 6: 4}
 # The all-orders kernel computes the delay and interpolation once (18 slots),
 # the roots of every order from shared transcendentals, and one add per
 # distinct power sum (1, 3, 5, 8, 12, 15 sums for orders up to 1..6).
@@ -56,6 +63,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="plain: skip the batched-launch comparison")
     ap.add_argument("--no-mirror", action="store_true", help="plain: skip the mirror-paired comparison")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="plain: skip measuring the device's issue and copy rates (the measured ceilings)")
     ap.add_argument("--no-tune", action="store_true", help="batch: default tilings instead of the autotuner's")
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "hodmas_tune_cache.jsonl"),
                     help="batch and plain mirror pairs: autotuner cache file (JSON lines)")
@@ -235,6 +244,23 @@ def bench_plain(args, torch):
                     "tilings": m_tiling,
                     "speedup_vs_unpaired": {str(k): round(per_order_ms[k] * 1e3 / m_us[k], 3) for k in orders}}
 
+    # ceilings from the measured issue rates of this device (unpacked FP32 add,
+    # the mean of the four transcendentals) and its HBM copy rate
+    measured = None
+    if not args.no_peaks:
+        pk = hodmas.measure_peaks(stream=stream)
+        r_v = pk["fp32_add"]
+        r_t = (pk["exp2"] + pk["log2"] + pk["sqrt"] + pk["rcp"]) / 4.0
+        ceil = {k: 1e3 / (NONTRANS[k] / r_v + TRANS[k] / r_t) for k in orders}   # Gpixel*ch/s
+        got = {k: pixch / (per_order_ms[k] * 1e-3) / 1e9 for k in orders}
+        measured = {"fp32_add_tlane_s": round(r_v, 2), "fp32_fma_tlane_s": round(pk["fp32_fma"], 2),
+                    "fp32_fma_sgpr_tlane_s": round(pk["fp32_fma_sgpr"], 2),
+                    "trans_tlane_s": {n: round(pk[n], 2) for n in ("exp2", "log2", "sqrt", "rcp")},
+                    "hbm_copy_tb_s": round(pk["hbm_copy_tb_s"], 3),
+                    "ceiling_gpixch_s": {str(k): round(v, 1) for k, v in ceil.items()},
+                    "frac_of_ceiling": {str(k): round(got[k] / ceil[k], 4) for k in orders},
+                    "frac_dominant": round(got[dom] / ceil[dom], 4)}
+
     # relative L2 of the last images against the oracle is checked by the tests;
     # here only the CPU oracle's throughput on the same batch is measured.
     cpu = None
@@ -281,7 +307,8 @@ def bench_plain(args, torch):
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),
                      "slots_per_pixch": SLOTS[dom], "traffic": _profiled_traffic(dom_kernel),
-                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)"},
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "measured": measured},
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }

@@ -371,6 +371,30 @@ hodmas_status hodmas_image_metrics(const float* image_dev, int32_t nx, int32_t n
                                    const hodmas_rect* target, const hodmas_rect* background,
                                    int32_t bins, void* stream, hodmas_metrics* out);
 
+/* ---------------------------------------------------------------------------
+ * Measured peaks of the current device, the ceilings the beamformer's
+ * rooflines are taken against (the path is bound by plain ALU issue; HBM is
+ * reported for completeness).  Not part of the paper's method: measurement
+ * infrastructure.  Rates are lane-operations per second in units of 1e12 (one
+ * wave64 instruction = 64 lane-operations), each from eight independent
+ * dependency chains per lane at eight waves per SIMD; packed FP32 is not
+ * measured (the library does not use it).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double fp32_add;        /* v_add_f32, all operands in VGPRs */
+    double fp32_fma;        /* v_fma_f32, all operands in VGPRs */
+    double fp32_fma_sgpr;   /* v_fma_f32 with one wave-uniform (SGPR) operand */
+    double exp2, log2, sqrt, rcp;   /* the transcendental unit */
+    double hbm_copy_tb_s;   /* 1 GiB device-to-device copy: bytes read + written, 1e12/s */
+    int32_t compute_units;
+} hodmas_peaks;
+
+/* Run the probes on the current device, on `stream`, and wait for them (about
+ * a second).  Allocates about 2 GiB of device memory for the copy and frees it
+ * before returning: a calibration call, not for the hot path.
+ * Errors: EINVAL (null out), ENOMEM, EDEVICE. */
+hodmas_status hodmas_measure_peaks(hodmas_peaks* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-Wall",
           "-I" + os.path.join(ROOT, "include")]
 SOURCES = ["hodmas_host.cpp", "hodmas_batch.cpp", "hodmas_tune.cpp", "hodmas_kernels.hip", "hodmas_display.hip",
-           "hodmas_metrics.hip"]
+           "hodmas_metrics.hip", "hodmas_probe.hip"]
 
 
 def _run(cmd):

@@ -97,6 +97,12 @@ class Metrics(ctypes.Structure):
                 ("sigma_out", ctypes.c_double)]
 
 
+class Peaks(ctypes.Structure):
+    _fields_ = [("fp32_add", ctypes.c_double), ("fp32_fma", ctypes.c_double), ("fp32_fma_sgpr", ctypes.c_double),
+                ("exp2", ctypes.c_double), ("log2", ctypes.c_double), ("sqrt", ctypes.c_double),
+                ("rcp", ctypes.c_double), ("hbm_copy_tb_s", ctypes.c_double), ("compute_units", ctypes.c_int32)]
+
+
 class DisplayDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("dz_m", ctypes.c_double),
                 ("sound_speed_m_s", ctypes.c_double), ("f_lo_hz", ctypes.c_double),
@@ -168,6 +174,8 @@ def _load():
     L.hodmas_image_metrics.restype = i32
     L.hodmas_image_metrics.argtypes = [vp, i32, i32, ctypes.c_double, ctypes.POINTER(Rect), ctypes.POINTER(Rect),
                                        i32, vp, ctypes.POINTER(Metrics)]
+    L.hodmas_measure_peaks.restype = i32
+    L.hodmas_measure_peaks.argtypes = [ctypes.POINTER(Peaks), vp]
     return L
 
 
@@ -454,3 +462,11 @@ def image_metrics(image, dx_m, target, background, bins=256, stream=None):
                                     ctypes.byref(t), ctypes.byref(b), int(bins), _stream_handle(stream),
                                     ctypes.byref(m)), "hodmas_image_metrics")
     return {f: getattr(m, f) for f, _ in Metrics._fields_}
+
+
+def measure_peaks(stream=None):
+    """Measured VALU issue rates (1e12 lane-operations/s) and HBM copy rate
+    (1e12 B/s) of the current device (see hodmas_measure_peaks)."""
+    p = Peaks()
+    _check(lib.hodmas_measure_peaks(ctypes.byref(p), _stream_handle(stream)), "hodmas_measure_peaks")
+    return {f: getattr(p, f) for f, _ in Peaks._fields_}

@@ -22,7 +22,7 @@ def test_autotune_cache_and_parity(tmp_path):
     til = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 4, cache_path=cache)
     first = time.perf_counter() - t0
     tx, tz, split, chunk = til
-    assert tx * tz * split == 256 and split in (1, 2, 4) and chunk >= 1
+    assert tx * tz * split in (256, 512) and split in (1, 2, 4) and chunk >= 1
     assert os.path.exists(cache) and til == tuple(__import__("json").loads(open(cache).readline())["tiling"])
     t0 = time.perf_counter()
     again = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 4, cache_path=cache)
@@ -31,5 +31,28 @@ def test_autotune_cache_and_parity(tmp_path):
     arr = ph.to_fp32(f.rf)
     img = plan.beamform(torch.from_numpy(arr).cuda(), 4).cpu().numpy().astype(np.float64)
     ref = O.beamform(arr, f.geometry, f.grid, 4)
+    assert np.linalg.norm(img - ref) / np.linalg.norm(ref) <= 1e-5
+    plan.close()
+
+
+def test_autotune_mirror_pairs(tmp_path):
+    """With HODMAS_FLAG_MIRROR the tuner keeps only tilings the pairing accepts
+    (whole, even tile columns), caches them under their own key, and the tuned
+    paired plan keeps parity."""
+    assert torch.cuda.is_available()
+    from paper_2203_14906_amd import hodmas
+    f = ph.config_frame(1)
+    cache = str(tmp_path / "tune.jsonl")
+    plain = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 2, cache_path=cache)
+    til = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 2, flags=hodmas.FLAG_MIRROR, cache_path=cache)
+    tx = til[0]
+    assert f.grid.nx % tx == 0 and (f.grid.nx // tx) % 2 == 0
+    keys = [__import__("json").loads(l)["key"] for l in open(cache)]
+    assert len(keys) == 2 and keys[0] != keys[1]
+    assert hodmas.autotune(f.geometry, f.grid, 1024, "f32", 2, cache_path=cache) == plain
+    plan = hodmas.Plan(f.geometry, f.grid, 1024, "f32", max_order=2, tiling=til, flags=hodmas.FLAG_MIRROR)
+    arr = ph.to_fp32(f.rf)
+    img = plan.beamform(torch.from_numpy(arr).cuda(), 2).cpu().numpy().astype(np.float64)
+    ref = O.beamform(arr, f.geometry, f.grid, 2)
     assert np.linalg.norm(img - ref) / np.linalg.norm(ref) <= 1e-5
     plan.close()
