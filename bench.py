@@ -47,8 +47,9 @@ FUSED_SLOTS = {1: 19, 2: 26, 3: 38, 4: 47, 5: 59, 6: 68}
 
 def parse():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="plain", choices=["plain", "reduced", "batch", "serve", "display"],
-                    help="plain: 128 el / 512^2 / FP32 (default); reduced: 256 el / 1024^2 / int16+FP16; "
+    ap.add_argument("--workload", default="plain", choices=["plain", "small", "reduced", "batch", "serve", "display"],
+                    help="plain: 128 el / 512^2 / FP32 (default); small: 64 el / 128^2 / FP32 latency and "
+                         "back-to-back throughput; reduced: 256 el / 1024^2 / int16+FP16; "
                          "batch: 256 mixed FP16 frames in one persistent launch vs 256 FP32 launches; "
                          "serve: Poisson arrivals, continuous batching vs plain FP32 per request; "
                          "display: band-pass + Hilbert envelope + log compression of beamformed images")
@@ -81,7 +82,7 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    {"plain": bench_plain, "reduced": bench_reduced, "batch": bench_batch,
+    {"plain": bench_plain, "small": bench_small, "reduced": bench_reduced, "batch": bench_batch,
      "serve": bench_serve, "display": bench_display}[args.workload](args, torch)
 
 
@@ -314,6 +315,85 @@ def bench_plain(args, torch):
     }
     print(json.dumps(res))
     plan.close()
+
+
+def bench_small(args, torch):
+    """Config 1: 64 elements, 1024 samples, 128x128 grid, FP32 RF, orders 1..4.
+    A frame is about a microsecond of GPU work, so one launch is bound by launch
+    overhead: report single-launch latency (host wall clock of launch plus
+    synchronize, and the kernel's own time from HIP events) and throughput over
+    1024 back-to-back frames, as per-frame launches and as one persistent batch
+    launch replayed from a HIP graph."""
+    from paper_2203_14906_amd import hodmas, phantom as ph
+    dev = torch.device("cuda:0")
+    p = ph.CONFIGS[1]
+    orders = list(p["orders"])
+    n_res, n_frames = 16, 1024                    # resident records, frames per throughput run
+    frames = [ph.config_frame(1, b) for b in range(n_res)]
+    geom, grid = frames[0].geometry, frames[0].grid
+    pixch = grid.nx * grid.nz * p["n_elements"]
+    plan = hodmas.Plan(geom, grid, p["n_samples"], "f32", max_order=max(orders))
+    info = plan.info()
+    rf = [torch.from_numpy(ph.to_fp32(fr.rf)).to(dev) for fr in frames]
+    outs = [torch.empty((grid.nz, grid.nx), dtype=torch.float32, device=dev) for _ in range(n_frames)]
+    stream = torch.cuda.current_stream()
+    res = {"metric": "config-1 single-launch latency and back-to-back throughput", "unit": "us / Gpixel*ch/s",
+           "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "64 elements, 1024 samples/channel, 128x128 grid, FP32 RF, orders 1-4",
+                      "tiling": [info.tiling.tile_x, info.tiling.tile_z, info.tiling.split, info.tiling.chunk],
+                      "n_tiles": info.n_tiles, "frames_back_to_back": n_frames},
+           "per_order": {}}
+    bt = hodmas.Batch(max_frames=n_frames, max_units=info.n_tiles * n_frames, max_lds_bytes=info.lds_bytes)
+    for k in orders:
+        for _ in range(max(3, args.warmup)):
+            plan.beamform(rf[0], k, outs[0], stream=stream)
+        torch.cuda.synchronize()
+        wall = []
+        for r in range(200):
+            t0 = time.perf_counter()
+            plan.beamform(rf[r % n_res], k, outs[0], stream=stream)
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e6)
+        ev = _events(torch, 200)
+        for r in range(200):
+            ev[r][0].record(stream)
+            plan.beamform(rf[r % n_res], k, outs[0], stream=stream)
+            ev[r][1].record(stream)
+        torch.cuda.synchronize()
+        kern = sorted(a.elapsed_time(z) * 1e3 for a, z in ev)
+        # back-to-back: n_frames launches, one event pair around them
+        e0, e1 = _events(torch, 1)[0]
+        e0.record(stream)
+        for i in range(n_frames):
+            plan.beamform(rf[i % n_res], k, outs[i], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        b2b_ms = e0.elapsed_time(e1)
+        # the same frames as one persistent launch, replayed from a graph
+        bt.set([plan] * n_frames, [rf[i % n_res] for i in range(n_frames)], [k] * n_frames, outs)
+        bt.capture()
+        for _ in range(2):
+            bt.replay(stream=stream)
+        torch.cuda.synchronize()
+        bev = _events(torch, max(1, args.steps))
+        for b in bev:
+            b[0].record(stream)
+            bt.replay(stream=stream)
+            b[1].record(stream)
+        torch.cuda.synchronize()
+        batch_ms = sorted(a.elapsed_time(z) for a, z in bev)[len(bev) // 2]
+        wall.sort()
+        res["per_order"][str(k)] = {
+            "latency_wall_us_p50": round(wall[len(wall) // 2], 2),
+            "latency_wall_us_p99": round(wall[int(0.99 * (len(wall) - 1))], 2),
+            "kernel_us_p50": round(kern[len(kern) // 2], 2),
+            "back_to_back_us_per_frame": round(b2b_ms * 1e3 / n_frames, 3),
+            "back_to_back_gpixch_s": round(pixch * n_frames / (b2b_ms * 1e-3) / 1e9, 2),
+            "batched_us_per_frame": round(batch_ms * 1e3 / n_frames, 3),
+            "batched_gpixch_s": round(pixch * n_frames / (batch_ms * 1e-3) / 1e9, 2)}
+    bt.close()
+    plan.close()
+    print(json.dumps(res))
 
 
 def bench_reduced(args, torch):

@@ -271,9 +271,13 @@ hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
 hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
 
 /* Build (once) a HIP graph chaining the persistent kernels of every kind; they
- * read the work list from device memory (a kind absent from it returns at
- * once), so later hodmas_batch_set calls need no re-capture.
- * hodmas_batch_replay launches that graph on `stream`. */
+ * read the work list from device memory, so later hodmas_batch_set calls need
+ * no re-capture.  hodmas_batch_replay launches that graph on `stream`, after
+ * fitting the instantiated graph to the current work list: kinds absent from
+ * it are switched off and each present kind runs at most one workgroup per
+ * unit.  When that changes a node, the replay first waits for the previous
+ * replay of the graph to finish (host-side); replays of an unchanged kind mix
+ * do not wait. */
 hodmas_status hodmas_batch_capture(hodmas_batch_t batch);
 hodmas_status hodmas_batch_replay(hodmas_batch_t batch, void* stream);
 

@@ -44,6 +44,11 @@ struct hodmas_batch_s {
     int32_t begin[hodmas::kBatchKinds] = {}, end[hodmas::kBatchKinds] = {};   // host copy of the ranges
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node[hodmas::kBatchKinds] = {};   // one kernel node per kind
+    int node_grid[hodmas::kBatchKinds] = {};         // its current grid in `exec`
+    bool node_on[hodmas::kBatchKinds] = {};          // enabled in `exec`
+    hipEvent_t replayed = nullptr;   // the last replay's completion
+    bool replay_pending = false;
     hodmas_batch_info info{};
 };
 
@@ -51,6 +56,10 @@ namespace {
 
 void release(hodmas_batch_s* b)
 {
+    if (b->replayed) {
+        (void)hipEventSynchronize(b->replayed);
+        (void)hipEventDestroy(b->replayed);
+    }
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->copied) {
@@ -61,6 +70,7 @@ void release(hodmas_batch_s* b)
     if (b->h_buf) (void)hipHostFree(b->h_buf);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->replayed = nullptr;
     b->copied = nullptr;
     b->d_buf = nullptr;
     b->h_buf = nullptr;
@@ -253,8 +263,28 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
 }
 
 // The graph chains one node per kind; each reads its unit range from the
-// device header, so a node whose kind is absent from the current work list
-// returns at once and later hodmas_batch_set calls need no re-capture.
+// device header, so later hodmas_batch_set calls need no re-capture.  Before
+// each replay the nodes are fitted to the current work list in the
+// instantiated graph itself: a kind that is absent is switched off (a
+// persistent grid that only finds nothing to do still costs microseconds),
+// and a present kind gets no more workgroups than it has units.
+namespace {
+
+hipKernelNodeParams node_params(const hodmas_batch_s* b, int order, int dtype, int grid, void** args)
+{
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.func = const_cast<void*>(hodmas::batch_kernel(order, dtype, !(b->flags & HODMAS_FLAG_ACC_PLAIN)));
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(hodmas::kBlock);
+    kp.sharedMemBytes = (unsigned)b->lds_bytes;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return kp;
+}
+
+}  // namespace
+
 hodmas_status hodmas_batch_capture(hodmas_batch_t b)
 {
     if (!valid_batch(b))
@@ -265,27 +295,25 @@ hodmas_status hodmas_batch_capture(hodmas_batch_t b)
     const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
-    const bool comp = !(b->flags & HODMAS_FLAG_ACC_PLAIN);
     bool ok = hipGraphCreate(&b->graph, 0) == hipSuccess;
     hipGraphNode_t prev = nullptr;
     for (int k = 1; k <= HODMAS_MAX_ORDER && ok; ++k) {
         for (int dt = 0; dt < 3 && ok; ++dt) {
-            hipKernelNodeParams kp;
-            std::memset(&kp, 0, sizeof(kp));
-            kp.func = const_cast<void*>(hodmas::batch_kernel(k, dt, comp));
-            kp.gridDim = dim3(b->grid[hodmas::batch_kind(k, dt)]);
-            kp.blockDim = dim3(hodmas::kBlock);
-            kp.sharedMemBytes = (unsigned)b->lds_bytes;
-            kp.kernelParams = args;
-            kp.extra = nullptr;
+            const int kind = hodmas::batch_kind(k, dt);
+            const hipKernelNodeParams kp = node_params(b, k, dt, b->grid[kind], args);
             hipGraphNode_t node = nullptr;
             ok = hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp) ==
                  hipSuccess;
+            b->node[kind] = node;
+            b->node_grid[kind] = b->grid[kind];
+            b->node_on[kind] = true;
             prev = node;
         }
     }
     if (ok)
         ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (ok && !b->replayed)
+        ok = hipEventCreateWithFlags(&b->replayed, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -300,10 +328,55 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
 {
     if (!valid_batch(b) || !b->exec || !b->has_list)
         return HODMAS_EINVAL;
-    if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess) {
+    const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(b->d_buf);
+    const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
+    const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
+    void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
+    // a launch of `exec` still in flight must not see its nodes change
+    bool change = false;
+    for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
+        const int n = b->end[kind] - b->begin[kind];
+        change = change || (n > 0) != b->node_on[kind] ||
+                 (n > 0 && (int)std::min<int64_t>(b->grid[kind], n) != b->node_grid[kind]);
+    }
+    if (change && b->replay_pending) {
+        if (hipEventSynchronize(b->replayed) != hipSuccess) {
+            (void)hipGetLastError();
+            return HODMAS_EDEVICE;
+        }
+        b->replay_pending = false;
+    }
+    for (int k = 1; k <= HODMAS_MAX_ORDER && change; ++k) {
+        for (int dt = 0; dt < 3; ++dt) {
+            const int kind = hodmas::batch_kind(k, dt);
+            const int n = b->end[kind] - b->begin[kind];
+            const bool on = n > 0;
+            if (on) {
+                const int grid = (int)std::min<int64_t>(b->grid[kind], n);
+                if (grid != b->node_grid[kind]) {
+                    const hipKernelNodeParams kp = node_params(b, k, dt, grid, args);
+                    if (hipGraphExecKernelNodeSetParams(b->exec, b->node[kind], &kp) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return HODMAS_EDEVICE;
+                    }
+                    b->node_grid[kind] = grid;
+                }
+            }
+            if (on != b->node_on[kind]) {
+                if (hipGraphNodeSetEnabled(b->exec, b->node[kind], on ? 1 : 0) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return HODMAS_EDEVICE;
+                }
+                b->node_on[kind] = on;
+            }
+        }
+    }
+    if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess ||
+        hipEventRecord(b->replayed, static_cast<hipStream_t>(stream)) != hipSuccess) {
         (void)hipGetLastError();
         return HODMAS_EDEVICE;
     }
+    b->replay_pending = true;
     return HODMAS_OK;
 }
 

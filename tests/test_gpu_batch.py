@@ -106,6 +106,33 @@ def test_graph_replays_and_reset_work_list(hd):
         p.close()
 
 
+def test_graph_replays_follow_changing_kind_mixes(hd):
+    """Replays fit the instantiated graph to each work list (absent kinds
+    switched off, grids cut to the unit count): a kind that leaves and comes
+    back, a single tiny frame, and back-to-back replays without a host wait
+    all give every frame its own launch's image."""
+    plans, rfs, outs, orders, _ = make_batch_inputs(hd, SPECS, seed0=900)
+    alone = [p.beamform(r, k).clone() for p, r, k in zip(plans, rfs, orders)]
+    batch = hd.Batch(max_frames=16, max_units=100000)
+    batch.set(plans, rfs, orders, outs)
+    batch.capture()
+    picks = [list(range(len(SPECS))), [2, 8], [9], [4, 0], list(range(len(SPECS))), [7]]
+    for step, idx in enumerate(picks):
+        for i in idx:
+            outs[i].fill_(float("nan"))
+        batch.set([plans[i] for i in idx], [rfs[i] for i in idx], [orders[i] for i in idx],
+                  [outs[i] for i in idx])
+        for _ in range(3):                       # replays queued back to back
+            batch.replay()
+        torch.cuda.synchronize()
+        for i in idx:
+            assert torch.equal(alone[i], outs[i]), "step %d frame %d" % (step, i)
+        say("replay step %d (frames %s) ok" % (step, idx))
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 @pytest.mark.parametrize("comp", [True, False])
 def test_batch_multi_chunk_split_and_batch_lds(hd, comp):
     # units of several chunks, split tilings (combined through LDS between
