@@ -17,6 +17,8 @@
 // Per-element constants are wave-uniform (every lane of a wave works on the same
 // element at the same time), so they live in SGPRs via scalar loads; the
 // per-pixel state lives in VGPRs.  No MFMA: this is gather + VALU work.
+// Template parameter M = 2 pairs each pixel with its mirror image about x = 0
+// (one delay serves both; see process_tile).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
