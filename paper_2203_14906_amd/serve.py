@@ -8,6 +8,9 @@ on that slot's stream -- as one batched submission, or as the frame's own
 kernel when only one is waiting -- while earlier slots may still be running,
 so work from different arrivals overlaps on the GPU.
 Completion is observed through HIP events; latency = completion - arrival.
+A failure stays with its request: unknown frames and orders outside 1..6 are
+rejected on arrival, requests whose deadline passes before launch are
+dropped, and a refused batched launch is retried one request at a time.
 
 The plain comparison runs one synchronous float32 hodmas_beamform per request
 in arrival order on one stream.
@@ -31,21 +34,13 @@ class Request:
     arrival: float            # seconds from the start of the run
     frame: int                # index into the frame pool
     order: int
-    done: float = -1.0        # completion time, seconds from the start
+    deadline: float | None = None   # seconds after arrival by which it must have launched
+    done: float = -1.0        # completion (or rejection / drop / failure) time, from the start
+    status: str = "pending"   # done | rejected | dropped | failed
     image: object = None      # device tensor
     nbytes: int = 0
     waited: bool = False      # held back at least once by the HBM budget
-
-
-@dataclass
-class PoolFrame:
-    n_elements: int
-    n_samples: int
-    side: int
-    rf16: object               # device float16 [N][S]
-    rf32: object               # device float32 [N][S]
-    plan16: object = None
-    plan32: object = None
+    solo: bool = False        # to be launched alone (its batch failed to launch)
 
 
 @dataclass
@@ -57,16 +52,32 @@ class ServeStats:
     launches: int = 0
     max_inflight: int = 0
     admission_waits: int = 0     # requests held back at least once by the budget
+    rejected: int = 0            # refused on arrival (unknown frame, order outside 1..6)
+    dropped: int = 0             # deadline passed before launch
+    failed: int = 0              # the library refused the launch of this request
 
     def summary(self) -> dict:
         lat = self.latencies_ms
+        served = self.n_requests - self.rejected - self.dropped - self.failed
         return {"mode": self.mode, "requests": self.n_requests,
-                "frames_per_s": round(self.n_requests / self.wall_s, 2) if self.wall_s > 0 else None,
+                "frames_per_s": round(served / self.wall_s, 2) if self.wall_s > 0 else None,
                 "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
                 "p99_ms": round(float(np.percentile(lat, 99)), 3) if lat.size else None,
                 "mean_ms": round(float(lat.mean()), 3) if lat.size else None,
                 "launches": self.launches, "max_inflight_requests": self.max_inflight,
-                "admission_waits": self.admission_waits}
+                "admission_waits": self.admission_waits, "rejected": self.rejected,
+                "dropped": self.dropped, "failed": self.failed}
+
+
+@dataclass
+class PoolFrame:
+    n_elements: int
+    n_samples: int
+    side: int
+    rf16: object               # device float16 [N][S]
+    rf32: object               # device float32 [N][S]
+    plan16: object = None
+    plan32: object = None
 
 
 class FramePool:
@@ -128,102 +139,190 @@ def poisson_requests(rate_hz, duration_s, n_frames, seed=0, orders=(1, 2, 3, 4, 
     return out
 
 
-class Server:
-    """Slots x streams continuous batching with HBM-budget admission."""
+class LaunchError(RuntimeError):
+    """An executor could not enqueue a launch (nothing of it was enqueued)."""
 
-    def __init__(self, torch, pool: FramePool, slots=3, budget_bytes=32 << 30, max_batch=64,
-                 max_units=1 << 20):
+
+class TorchExecutor:
+    """Launch slots on the GPU: each slot owns a stream and a batch object;
+    a launch of one request runs its frame's own kernel, of several one
+    batched submission.  Completion is a HIP event on the slot's stream."""
+
+    def __init__(self, torch, pool, slots=3, max_batch=64, max_units=1 << 20):
         self.torch = torch
         self.pool = pool
-        self.budget = int(budget_bytes)
-        self.max_batch = int(max_batch)
         lds = pool.max_lds_bytes
-        self.slots = []
-        for _ in range(slots):
-            b = hodmas.Batch(max_frames=max_batch, max_units=max_units, max_lds_bytes=lds)
-            self.slots.append({"batch": b, "stream": torch.cuda.Stream(), "event": None,
-                               "reqs": []})
+        self.slots = [{"batch": hodmas.Batch(max_frames=max_batch, max_units=max_units, max_lds_bytes=lds),
+                       "stream": torch.cuda.Stream()} for _ in range(slots)]
+
+    @property
+    def n_slots(self):
+        return len(self.slots)
+
+    def launch(self, slot, reqs):
+        torch, s = self.torch, self.slots[slot]
+        frs = [self.pool.frames[r.frame] for r in reqs]
+        for r, fr in zip(reqs, frs):
+            if r.image is None:
+                r.image = torch.empty((fr.side, fr.side), dtype=torch.float32, device="cuda")
+        try:
+            if len(reqs) == 1:
+                frs[0].plan16.beamform(frs[0].rf16, reqs[0].order, reqs[0].image, stream=s["stream"])
+            else:
+                b = s["batch"]
+                b.set([f.plan16 for f in frs], [f.rf16 for f in frs], [r.order for r in reqs],
+                      [r.image for r in reqs], stream=s["stream"])
+                b.launch(stream=s["stream"])
+        except (hodmas.HodmasError, ValueError) as e:
+            raise LaunchError(str(e)) from e
+        ev = torch.cuda.Event()
+        ev.record(s["stream"])
+        return ev
+
+    @staticmethod
+    def done(handle):
+        return handle.query()
 
     def close(self):
         for s in self.slots:
             s["batch"].close()
         self.slots = []
 
+
+class Server:
+    """Slots x streams continuous batching with HBM-budget admission.
+
+    Requests are admitted in arrival order while their footprint fits the
+    budget; whenever a launch slot is free, everything admitted goes out on it.
+    Failures stay with their own request: an unknown frame or an order outside
+    1..6 is rejected on arrival, a request whose deadline passes before launch
+    is dropped, and when a batched launch is refused its requests are launched
+    one by one, so only the request the library refuses fails.  The scheduling
+    here is host logic over an executor (by default the GPU one above)."""
+
+    def __init__(self, torch, pool, slots=3, budget_bytes=32 << 30, max_batch=64, max_units=1 << 20,
+                 executor=None, clock=time.perf_counter, sleep=time.sleep):
+        self.pool = pool
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch)
+        self.executor = executor if executor is not None else TorchExecutor(torch, pool, slots, max_batch,
+                                                                             max_units)
+        self.clock, self.sleep = clock, sleep
+
+    def close(self):
+        if isinstance(self.executor, TorchExecutor):
+            self.executor.close()
+
     def _footprint(self, r: Request) -> int:
         fr = self.pool.frames[r.frame]
         return fr.side * fr.side * 4 + fr.n_elements * fr.n_samples * 2
 
+    def _valid(self, r: Request) -> bool:
+        return 0 <= r.frame < len(self.pool.frames) and 1 <= r.order <= hodmas.MAX_ORDER
+
+    @staticmethod
+    def _expired(r: Request, now: float) -> bool:
+        return r.deadline is not None and now - r.arrival > r.deadline
+
     def run(self, requests: list[Request], keep_images=False) -> ServeStats:
-        torch = self.torch
+        ex = self.executor
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         admitted: deque = deque()
-        inflight_bytes = 0
-        inflight_reqs = 0
+        inflight = [None] * ex.n_slots          # (completion handle, requests) per slot
+        state = {"bytes": 0, "reqs": 0, "finished": 0}
         stats = ServeStats("batched", len(requests), 0.0)
         total = len(requests)
-        finished = 0
-        t0 = time.perf_counter()
-        while finished < total:
-            now = time.perf_counter() - t0
+        t0 = self.clock()
+
+        def finish(r, status, now):
+            r.status, r.done = status, now
+            state["bytes"] -= r.nbytes
+            r.nbytes = 0
+            state["finished"] += 1
+            if status != "done" or not keep_images:
+                r.image = None
+
+        while state["finished"] < total:
+            now = self.clock() - t0
             # completions
-            for s in self.slots:
-                if s["event"] is not None and s["event"].query():
-                    for r in s["reqs"]:
-                        r.done = now
-                        inflight_bytes -= r.nbytes
-                        if not keep_images:
-                            r.image = None
-                    finished += len(s["reqs"])
-                    inflight_reqs -= len(s["reqs"])
-                    s["event"], s["reqs"] = None, []
-            # arrivals -> admission by HBM budget (in arrival order)
+            for i, slot in enumerate(inflight):
+                if slot is not None and ex.done(slot[0]):
+                    for r in slot[1]:
+                        finish(r, "done", now)
+                    state["reqs"] -= len(slot[1])
+                    inflight[i] = None
+            # arrivals -> validation, deadlines, admission by HBM budget (in arrival order)
             while pending and pending[0].arrival <= now:
                 r = pending[0]
+                if not self._valid(r):
+                    pending.popleft()
+                    finish(r, "rejected", now)
+                    stats.rejected += 1
+                    continue
+                if self._expired(r, now):
+                    pending.popleft()
+                    finish(r, "dropped", now)
+                    stats.dropped += 1
+                    continue
                 nb = self._footprint(r)
-                if inflight_bytes + nb > self.budget and (inflight_bytes > 0 or admitted):
+                if state["bytes"] + nb > self.budget and (state["bytes"] > 0 or admitted):
                     if not r.waited:
                         r.waited = True
                         stats.admission_waits += 1
                     break
                 pending.popleft()
                 r.nbytes = nb
-                inflight_bytes += nb
-                fr = self.pool.frames[r.frame]
-                r.image = torch.empty((fr.side, fr.side), dtype=torch.float32, device="cuda")
+                state["bytes"] += nb
                 admitted.append(r)
-            # a free slot takes everything admitted so far
+            # admitted requests whose deadline passed before a slot freed up
+            if admitted and any(r.deadline is not None for r in admitted):
+                keep = deque()
+                for r in admitted:
+                    if self._expired(r, now):
+                        finish(r, "dropped", now)
+                        stats.dropped += 1
+                    else:
+                        keep.append(r)
+                admitted = keep
+            # a free slot takes everything admitted so far (or one request marked solo)
             if admitted:
-                for s in self.slots:
-                    if s["event"] is None:
-                        take = [admitted.popleft() for _ in range(min(self.max_batch, len(admitted)))]
-                        frs = [self.pool.frames[r.frame] for r in take]
+                for i in range(len(inflight)):
+                    if inflight[i] is not None:
+                        continue
+                    if admitted[0].solo:
+                        take = [admitted.popleft()]
+                    else:
+                        take = []
+                        while admitted and not admitted[0].solo and len(take) < self.max_batch:
+                            take.append(admitted.popleft())
+                    try:
+                        handle = ex.launch(i, take)
+                    except LaunchError:
                         if len(take) == 1:
-                            # a lone request runs its frame's own kernel: no work list to build
-                            frs[0].plan16.beamform(frs[0].rf16, take[0].order, take[0].image,
-                                                   stream=s["stream"])
+                            finish(take[0], "failed", now)
+                            stats.failed += 1
                         else:
-                            b = s["batch"]
-                            b.set([f.plan16 for f in frs], [f.rf16 for f in frs], [r.order for r in take],
-                                  [r.image for r in take], stream=s["stream"])
-                            b.launch(stream=s["stream"])
-                        ev = torch.cuda.Event()
-                        ev.record(s["stream"])
-                        s["event"], s["reqs"] = ev, take
-                        inflight_reqs += len(take)
-                        stats.launches += 1
-                        stats.max_inflight = max(stats.max_inflight, inflight_reqs)
+                            for r in reversed(take):
+                                r.solo = True
+                                admitted.appendleft(r)
                         break
-            if finished < total:
+                    inflight[i] = (handle, take)
+                    state["reqs"] += len(take)
+                    stats.launches += 1
+                    stats.max_inflight = max(stats.max_inflight, state["reqs"])
+                    break
+            if state["finished"] < total:
                 # idle: sleep until shortly before the next arrival; with work in
                 # flight keep polling the completion events
                 nxt = pending[0].arrival if pending else None
-                busy = any(s["event"] is not None for s in self.slots)
+                busy = any(s is not None for s in inflight)
                 if not busy and not admitted and nxt is not None:
-                    delay = nxt - (time.perf_counter() - t0)
+                    delay = nxt - (self.clock() - t0)
                     if delay > 2e-4:
-                        time.sleep(delay - 1e-4)
-        stats.wall_s = max(r.done for r in requests) if requests else 0.0
-        stats.latencies_ms = np.array([(r.done - r.arrival) * 1e3 for r in requests])
+                        self.sleep(delay - 1e-4)
+        served = [r for r in requests if r.status == "done"]
+        stats.wall_s = max((r.done for r in served), default=0.0)
+        stats.latencies_ms = np.array([(r.done - r.arrival) * 1e3 for r in served])
         return stats
 
 
@@ -241,6 +340,7 @@ def run_plain(torch, pool: FramePool, requests: list[Request], keep_images=False
         fr.plan32.beamform(fr.rf32, r.order, r.image, stream=stream)
         stream.synchronize()
         r.done = time.perf_counter() - t0
+        r.status = "done"
         stats.launches += 1
         if not keep_images:
             r.image = None

@@ -142,6 +142,21 @@ def test_single_element_and_order_above_n(hd):
     plan.close()
 
 
+def test_one_pixel_grids_rows_and_columns(hd):
+    # tiles one pixel wide or deep: every other lane of the workgroup is idle
+    f = ph.make_frame(16, 400, 24, 24, n_points=4, seed=8)
+    arr = ph.to_fp32(f.rf)
+    for nx, nz in ((1, 1), (1, 37), (53, 1), (2, 3)):
+        grid = ph.Grid(nx=nx, nz=nz, x0_m=-0.3e-3, dx_m=0.2e-3, z0_m=3e-3, dz_m=0.15e-3)
+        for tiling in (None, (16, 16, 1, 0), (8, 8, 4, 5)):
+            plan = hd.Plan(f.geometry, grid, 400, "f32", max_order=6, tiling=tiling)
+            for k in (1, 2, 5, 6):
+                g = gpu_image(hd, plan, arr, k)
+                o = oracle_image(arr, 1.0, f.geometry, grid, k)
+                check(rel_l2(g, o), "f32", "grid %dx%d %s k=%d" % (nx, nz, tiling, k))
+            plan.close()
+
+
 def test_zero_rf_and_out_of_record(hd):
     g = ph.Geometry(16)
     grid = ph.make_grid(20, 20, 4.8e-3, 5e-3)

@@ -39,7 +39,7 @@ def test_server_results_equal_alone_and_admission(pool):
     torch.cuda.synchronize()
     summ = st.summary()
     say("batched:", summ)
-    assert all(r.done >= r.arrival for r in reqs)
+    assert all(r.done >= r.arrival and r.status == "done" for r in reqs)
     assert st.admission_waits > 0, "the tiny budget should make requests wait"
     assert st.launches > 1
     for r in reqs:
@@ -71,4 +71,22 @@ def test_plain_loop_and_overlap(pool):
     st = srv.run(reqs2)
     say("batched burst:", st.summary())
     assert st.max_inflight > 1
+    srv.close()
+
+
+def test_rejected_requests_leave_the_rest_intact(pool):
+    from paper_2203_14906_amd import serve
+    reqs = serve.poisson_requests(4000.0, 0.02, len(pool.frames), seed=6)
+    reqs[2].order, reqs[5].frame = 7, len(pool.frames) + 3
+    srv = serve.Server(torch, pool, slots=2, budget_bytes=32 << 30, max_batch=8)
+    st = srv.run(reqs, keep_images=True)
+    torch.cuda.synchronize()
+    say("with rejections:", st.summary())
+    assert st.rejected == 2 and reqs[2].status == reqs[5].status == "rejected"
+    for r in reqs:
+        if r.rid in (2, 5):
+            assert r.image is None
+            continue
+        fr = pool.frames[r.frame]
+        assert r.status == "done" and torch.equal(fr.plan16.beamform(fr.rf16, r.order), r.image)
     srv.close()
