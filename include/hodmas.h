@@ -142,6 +142,8 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
                           const hodmas_tiling* tiling, hodmas_plan_t* out);
 
 /* Beamform one frame at order k (1 = DAS, 2 = DMAS, 3..6 = DMAS-k; Eqs. 1-9).
+ * A plan is immutable after hodmas_plan: several host threads may launch with
+ * the same plan at once, on the same or different streams.
  * rf_dev: device pointer, channel-major records of the plan's dtype and stride.
  * image_dev: device float32 [nz][nx], fully overwritten.  Both are owned by the
  * caller and must stay valid until the work on `stream` completes.
@@ -167,6 +169,13 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
  * also when the combination of all power sums would not fit the LDS. */
 hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int32_t max_order,
                                      float* const* images_dev, void* stream);
+
+/* Wait for the work queued on `stream` (a hipStream_t; NULL = default stream)
+ * and report what the device made of it: HODMAS_OK, or HODMAS_EDEVICE when the
+ * stream's work or an earlier asynchronous launch failed.  Launch calls return
+ * only the errors known when they return; this is where asynchronous device
+ * errors surface. */
+hodmas_status hodmas_sync(void* stream);
 
 /* Release a plan and its device tables.  NULL is accepted.  The caller must
  * not destroy a plan while work launched with it may still be running. */

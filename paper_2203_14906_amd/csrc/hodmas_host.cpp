@@ -461,6 +461,13 @@ hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int
     return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
 }
 
+hodmas_status hodmas_sync(void* stream)
+{
+    const hipError_t a = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    const hipError_t b = hipGetLastError();   // also clears a sticky launch error
+    return a == hipSuccess && b == hipSuccess ? HODMAS_OK : HODMAS_EDEVICE;
+}
+
 hodmas_status hodmas_destroy(hodmas_plan_t plan)
 {
     if (!plan)

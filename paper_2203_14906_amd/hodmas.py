@@ -174,6 +174,8 @@ def _load():
     L.hodmas_image_metrics.restype = i32
     L.hodmas_image_metrics.argtypes = [vp, i32, i32, ctypes.c_double, ctypes.POINTER(Rect), ctypes.POINTER(Rect),
                                        i32, vp, ctypes.POINTER(Metrics)]
+    L.hodmas_sync.restype = i32
+    L.hodmas_sync.argtypes = [vp]
     L.hodmas_measure_peaks.restype = i32
     L.hodmas_measure_peaks.argtypes = [ctypes.POINTER(Peaks), vp]
     return L
@@ -470,3 +472,9 @@ def measure_peaks(stream=None):
     p = Peaks()
     _check(lib.hodmas_measure_peaks(ctypes.byref(p), _stream_handle(stream)), "hodmas_measure_peaks")
     return {f: getattr(p, f) for f, _ in Peaks._fields_}
+
+
+def sync(stream=None):
+    """Wait for `stream` and raise HodmasError if its work or an earlier
+    asynchronous launch failed (see hodmas_sync)."""
+    _check(lib.hodmas_sync(_stream_handle(stream)), "hodmas_sync")

@@ -265,6 +265,40 @@ def test_streams_and_concurrent_plans(hd):
     p2.close()
 
 
+def test_threads_share_a_plan(hd):
+    # the plan is immutable: four host threads launch with it at once, each on
+    # its own stream and frames, and every image equals the one-thread result
+    import threading
+    f = ph.make_frame(32, 512, 48, 40, n_points=3, seed=33)
+    plan = hd.Plan(f.geometry, f.grid, 512, "f32", max_order=6)
+    rfs = [torch.from_numpy(ph.to_fp32(ph.make_frame(32, 512, 48, 40, n_points=3, seed=40 + i).rf)).cuda()
+           for i in range(4)]
+    ref = {(i, k): plan.beamform(rfs[i], k).clone() for i in range(4) for k in (1, 3, 6)}
+    torch.cuda.synchronize()
+    got, errors = {}, []
+
+    def work(i):
+        try:
+            st = torch.cuda.Stream()
+            for rep in range(5):
+                for k in (1, 3, 6):
+                    got[(i, k, rep)] = plan.beamform(rfs[i], k, stream=st)
+            hd.sync(st)
+        except Exception as e:          # reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    hd.sync()
+    for (i, k, rep), img in got.items():
+        assert torch.equal(img, ref[(i, k)]), "thread %d order %d rep %d" % (i, k, rep)
+    plan.close()
+
+
 def test_maximum_sizes(hd):
     # the element-count limit, a long record and the widest grid side of this
     # build, on phantom RF (band-limited pulses in noise) at the 0.075 mm pixel
