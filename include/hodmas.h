@@ -279,9 +279,10 @@ hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
 /* Run the current work list on `stream`: one persistent launch per kind present. */
 hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
 
-/* Build (once) a HIP graph chaining the persistent kernels of every kind; they
- * read the work list from device memory, so later hodmas_batch_set calls need
- * no re-capture.  hodmas_batch_replay launches that graph on `stream`, after
+/* Build (once) a HIP graph holding the persistent kernels of every kind, with
+ * no order between them (kinds write disjoint images, so one kind's tail
+ * overlaps the next kind's start); they read the work list from device
+ * memory, so later hodmas_batch_set calls need no re-capture.  hodmas_batch_replay launches that graph on `stream`, after
  * fitting the instantiated graph to the current work list: kinds absent from
  * it are switched off and each present kind runs at most one workgroup per
  * unit.  When that changes a node, the replay first waits for the previous

@@ -262,8 +262,10 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
     return HODMAS_OK;
 }
 
-// The graph chains one node per kind; each reads its unit range from the
-// device header, so later hodmas_batch_set calls need no re-capture.  Before
+// The graph holds one node per kind and no edges between them: kinds write
+// disjoint images, so one kind's last units overlap the next kind's start
+// instead of the GPU draining between kinds.  Each node reads its unit range
+// from the device header, so later hodmas_batch_set calls need no re-capture.  Before
 // each replay the nodes are fitted to the current work list in the
 // instantiated graph itself: a kind that is absent is switched off (a
 // persistent grid that only finds nothing to do still costs microseconds),
@@ -296,18 +298,15 @@ hodmas_status hodmas_batch_capture(hodmas_batch_t b)
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
     bool ok = hipGraphCreate(&b->graph, 0) == hipSuccess;
-    hipGraphNode_t prev = nullptr;
     for (int k = 1; k <= HODMAS_MAX_ORDER && ok; ++k) {
         for (int dt = 0; dt < 3 && ok; ++dt) {
             const int kind = hodmas::batch_kind(k, dt);
             const hipKernelNodeParams kp = node_params(b, k, dt, b->grid[kind], args);
             hipGraphNode_t node = nullptr;
-            ok = hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp) ==
-                 hipSuccess;
+            ok = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) == hipSuccess;
             b->node[kind] = node;
             b->node_grid[kind] = b->grid[kind];
             b->node_on[kind] = true;
-            prev = node;
         }
     }
     if (ok)
