@@ -71,6 +71,8 @@ def test_plain_loop_and_overlap(pool):
     say("plain:", plain.summary())
     assert plain.latencies_ms.min() >= 0
     reqs2 = serve.poisson_requests(20000.0, 0.02, len(pool.frames), seed=5)
+    for r in reqs2[:96]:                      # a burst: launches queue up behind each other
+        r.arrival = reqs2[0].arrival
     srv = serve.Server(torch, pool, slots=3, budget_bytes=32 << 30, max_batch=4)
     st = srv.run(reqs2)
     say("batched burst:", st.summary())
