@@ -3,9 +3,11 @@
 
 Workload (default): 128-element array, 2048 samples per channel, 512 x 512
 grid, float32 RF, orders k = 1..6.  A step beamforms a batch of B resident
-frames (distinct seeds, already in HBM) at every order: B x 6 launches.  The
-metric is beamformed pixel-channel pairs per second (Gpixel*ch/s), summed
-over the orders, with the per-order rates beside it.
+frames (distinct seeds, already in HBM) at every order: one persistent batched
+launch per order over the B frames (--per-frame-step: B x 6 per-frame
+launches; the other form is timed beside it).  The metric is beamformed
+pixel-channel pairs per second (Gpixel*ch/s), summed over the orders, with
+the per-order rates beside it.
 
 Prints ONE JSON line.  Also reports:
   roofline      the dominant kernel (the order with the most device time) against
@@ -62,7 +64,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=8, help="frames per step")
     ap.add_argument("--orders", default="1,2,3,4,5,6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="plain: skip the batched-launch comparison")
+    ap.add_argument("--per-frame-step", action="store_true",
+                    help="plain: time one launch per frame and order instead of one batched launch per order")
+    ap.add_argument("--no-compare", action="store_true", help="plain: skip timing the other launch form")
     ap.add_argument("--no-mirror", action="store_true", help="plain: skip the mirror-paired comparison")
     ap.add_argument("--no-peaks", action="store_true",
                     help="plain: skip measuring the device's issue and copy rates (the measured ceilings)")
@@ -135,12 +139,36 @@ def bench_plain(args, torch):
         torch.cuda.synchronize()
         del src, dst
 
+    # A step beamforms the B resident frames at every order.  By default each
+    # order is one persistent batched launch over the B frames (their work
+    # lists are built here, outside the timed region; workgroups drift out of
+    # step, so one tile's staging overlaps another's arithmetic and the
+    # frames' tails overlap); --per-frame-step runs B per-frame launches per
+    # order instead.  The other form is timed beside it for comparison.
+    can_batch = info.tiling.tile_x * info.tiling.tile_z * info.tiling.split == 256
+    batched_step = can_batch and not args.per_frame_step
+    bts = {}
+    if can_batch and (batched_step or not args.no_compare):
+        for k in orders:
+            bt = hodmas.Batch(max_frames=args.batch, max_units=info.n_tiles * args.batch,
+                              max_lds_bytes=info.lds_bytes)
+            bt.set([plan] * args.batch, rf_dev, [k] * args.batch, out, stream=stream)
+            bts[k] = bt
+
+    def run_batched(k):
+        bts[k].launch(stream=stream)
+
+    def run_per_frame(k):
+        for b in range(args.batch):
+            plan.beamform(rf_dev[b], k, out[b], stream=stream)
+
+    run_order = run_batched if batched_step else run_per_frame
+
     def step(events=None):
         for k in orders:
             if events is not None:
                 events[k][0].record(stream)
-            for b in range(args.batch):
-                plan.beamform(rf_dev[b], k, out[b], stream=stream)
+            run_order(k)
             if events is not None:
                 events[k][1].record(stream)
 
@@ -163,7 +191,38 @@ def bench_plain(args, torch):
     value = total_pixch / elapsed / 1e9
     dom = max(orders, key=lambda k: per_order_ms[k])
     achieved = SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
-    dom_kernel = "hodmas_frame_kernel<%d, f32, %s>" % (dom, "comp")
+    dom_kernel = ("hodmas_batch_kernel<%d, f32, %s>" if batched_step else "hodmas_frame_kernel<%d, f32, %s>") % (
+        dom, "comp")
+
+    def time_form(run):
+        """Per-frame milliseconds of each order when its B frames run through `run`."""
+        ms = {}
+        for k in orders:
+            for _ in range(max(1, args.warmup)):
+                run(k)
+            fev = _events(torch, args.steps)
+            torch.cuda.synchronize()
+            for s_ in range(args.steps):
+                fev[s_][0].record(stream)
+                run(k)
+                fev[s_][1].record(stream)
+            torch.cuda.synchronize()
+            ms[k] = sum(a.elapsed_time(z) for a, z in fev) / (args.steps * args.batch)
+        return ms
+
+    # the other launch form of the same step
+    other = None
+    pf_ms = per_order_ms if not batched_step else None
+    if not args.no_compare and can_batch:
+        alt_ms = time_form(run_per_frame if batched_step else run_batched)
+        if batched_step:
+            pf_ms = alt_ms
+        other = {"form": "per-frame launches" if batched_step else "one batched launch per order",
+                 "kernel_us_per_frame": {str(k): round(v * 1e3, 3) for k, v in alt_ms.items()},
+                 "gpixch_s_sum_orders": round(pixch * len(orders) / (sum(alt_ms.values()) * 1e-3) / 1e9, 2),
+                 "headline_speedup": round(sum(alt_ms.values()) / sum(per_order_ms.values()), 3)}
+    for bt in bts.values():
+        bt.close()
 
     # every order 1..kmax from one launch per frame
     fused = None
@@ -186,35 +245,10 @@ def bench_plain(args, torch):
         f_ach = FUSED_SLOTS[kmax] * pixch / (f_ms * 1e-3) / 1e12
         fused = {"kernel": "hodmas_orders_kernel<%d, f32, comp>" % kmax, "kernel_us_per_frame": round(f_ms * 1e3, 2),
                  "gpixch_s_sum_orders": round(pixch * len(orders) / (f_ms * 1e-3) / 1e9, 2),
-                 "speedup_vs_per_order_launches": round(sum(per_order_ms.values()) / f_ms, 3),
+                 "speedup_vs_per_order_launches": (round(sum(pf_ms.values()) / f_ms, 3) if pf_ms else None),
                  "slots_per_pixch": FUSED_SLOTS[kmax], "achieved_tslot_s": round(f_ach, 2),
                  "frac": round(f_ach / VALU_PEAK_TSLOT, 4),
                  "traffic": _profiled_traffic("hodmas_orders_kernel<%d, f32, comp>" % kmax)}
-
-    # the same step through one persistent batch launch per order (the batch
-    # form's workgroups drift out of step, so one tile's staging overlaps
-    # another's arithmetic)
-    batched = None
-    if not args.no_batched and info.tiling.tile_x * info.tiling.tile_z * info.tiling.split == 256:
-        bt = hodmas.Batch(max_frames=args.batch, max_units=info.n_tiles * args.batch, max_lds_bytes=info.lds_bytes)
-        b_us = {}
-        for k in orders:
-            bt.set([plan] * args.batch, rf_dev, [k] * args.batch, out)
-            for _ in range(max(1, args.warmup)):
-                bt.launch(stream=stream)
-            bev = _events(torch, args.steps)
-            torch.cuda.synchronize()
-            for s_ in range(args.steps):
-                bev[s_][0].record(stream)
-                bt.launch(stream=stream)
-                bev[s_][1].record(stream)
-            torch.cuda.synchronize()
-            b_us[k] = sum(a.elapsed_time(z) for a, z in bev) / (args.steps * args.batch) * 1e3
-        b_tot = sum(b_us.values())
-        batched = {"kernel_us_per_frame": {str(k): round(v, 2) for k, v in b_us.items()},
-                   "gpixch_s_sum_orders": round(pixch * len(orders) / (b_tot * 1e-6) / 1e9, 2),
-                   "speedup_vs_per_frame_launches": round(sum(per_order_ms.values()) * 1e3 / b_tot, 3)}
-        bt.close()
 
     # mirror pairing: the array and the grid are symmetric about x = 0, so one
     # workgroup forms a tile and its mirror image from one set of delays
@@ -243,7 +277,8 @@ def bench_plain(args, torch):
         mirrored = {"kernel": "hodmas_frame_kernel<k, f32, comp, mirror pairs>",
                     "kernel_us_per_frame": {str(k): round(v, 2) for k, v in m_us.items()},
                     "tilings": m_tiling,
-                    "speedup_vs_unpaired": {str(k): round(per_order_ms[k] * 1e3 / m_us[k], 3) for k in orders}}
+                    "speedup_vs_unpaired_per_frame": ({str(k): round(pf_ms[k] * 1e3 / m_us[k], 3) for k in orders}
+                                                      if pf_ms else None)}
 
     # ceilings from the measured issue rates of this device (unpacked FP32 add,
     # the mean of the four transcendentals) and its HBM copy rate
@@ -301,14 +336,16 @@ def bench_plain(args, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "plain HO-DMAS, 128-element array, 2048 samples/channel, 512x512 grid, "
-                               "FP32 RF, orders 1-6, %d resident frames per step" % args.batch,
+                               "FP32 RF, orders 1-6, %d resident frames per step, %s" % (
+                                   args.batch, "each order one persistent batched launch over the frames"
+                                   if batched_step else "one launch per frame and order"),
                    "n_elements": n_el, "n_samples": S, "grid": [grid.nx, grid.nz],
                    "batch_frames": args.batch, "orders": orders,
                    "tiling": [info.tiling.tile_x, info.tiling.tile_z, info.tiling.split, info.tiling.chunk]},
         "per_order_gpixch_s": per_order,
         "per_order_kernel_us": {str(k): round(per_order_ms[k] * 1e3, 2) for k in orders},
         "fused_all_orders": fused,
-        "batched_per_order": batched,
+        "other_launch_form": other,
         "mirror_paired": mirrored,
         "roofline": {"bound": "alu", "kernel": dom_kernel,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
