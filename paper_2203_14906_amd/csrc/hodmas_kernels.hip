@@ -6,7 +6,7 @@
 //      workgroup staged with coalesced channel-major loads, and interpolates,
 //   3. takes the signed k-th root y = sign(s)|s|^(1/k)       (Eq. 2, Eqs. 4-6),
 //   4. accumulates the power sums p_j = sum y^j, j = 1..k, with compensated
-//      float32 summation (pairwise groups of four, Kahan steps per 16 elements),
+//      float32 summation (pairwise groups of four, Kahan steps per 32 elements),
 // and per pixel recovers the order-k symmetric sum e_k from p_1..p_k with
 // Newton's identities (the general form of Eqs. 3, 7, 8 and 9):
 //   e_0 = 1,  m e_m = sum_{j=1..m} (-1)^(j-1) e_{m-j} p_j.
@@ -98,9 +98,13 @@ __device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, floa
     const float d = __builtin_amdgcn_sqrtf(__builtin_fabsf(e.d0sq + num));
     const float r = __builtin_amdgcn_rcpf(d + e.d0);
     p.t = __builtin_fmaf(num, r, e.frac0);
-    const float fl = __builtin_floorf(p.t);
-    p.f = p.t - fl;
-    p.addr = ((int)fl << 2) + e.off;
+    // floor(t) as an integer in one instruction (the compiler emits a floor and
+    // a conversion), and t - floor(t), which is exact in float32, so fract
+    // returns it unchanged
+    int fl;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(p.t));
+    p.f = __builtin_amdgcn_fractf(p.t);
+    p.addr = (fl << 2) + e.off;
     return p;
 }
 
@@ -241,7 +245,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
 }
 
 // Power-sum accumulation.  Compensated mode: four elements are summed pairwise,
-// four such groups (16 elements) accumulate in a plain float32 partial, and the
+// eight such groups (32 elements) accumulate in a plain float32 partial, and the
 // partial enters the running sum with one Kahan step.  The rounding error then
 // stays at a few units of the partials' magnitude instead of growing with N.
 template <int K>
@@ -324,7 +328,7 @@ template <int NS, bool COMP, int M>
 __device__ __forceinline__ void after_group(int& groups, float (&s)[M][NS], float (&c)[M][NS],
                                             float (&P)[M][NS])
 {
-    if (COMP && (++groups & 3) == 0) {
+    if (COMP && (++groups & 7) == 0) {
 #pragma unroll
         for (int mm = 0; mm < M; ++mm)
             flush<NS>(s[mm], c[mm], P[mm]);
@@ -735,14 +739,14 @@ __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float 
         while (true) {
             const bool more_a = sl + 8 <= n;
             process_group_all<KMAX, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
-            if (COMP && (++groups & 3) == 0)
+            if (COMP && (++groups & 7) == 0)
                 flush_all<KMAX, COMP>(s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
             process_group_all<KMAX, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
-            if (COMP && (++groups & 3) == 0)
+            if (COMP && (++groups & 7) == 0)
                 flush_all<KMAX, COMP>(s, c, P);
             sl += 4;
             if (!more_b)
