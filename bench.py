@@ -5,7 +5,9 @@ Workload (default): 128-element array, 2048 samples per channel, 512 x 512
 grid, float32 RF, orders k = 1..6.  A step beamforms a batch of B resident
 frames (distinct seeds, already in HBM) at every order: one persistent batched
 launch per order over the B frames (--per-frame-step: B x 6 per-frame
-launches; the other form is timed beside it).  The metric is beamformed
+launches), with mirror pairs -- the array and the grid are symmetric about
+x = 0, so one workgroup forms a tile and its mirror image from one set of
+delays (--no-mirror: unpaired).  The unpaired forms are timed beside it.  The metric is beamformed
 pixel-channel pairs per second (Gpixel*ch/s), summed over the orders, with
 the per-order rates beside it.
 
@@ -66,8 +68,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-frame-step", action="store_true",
                     help="plain: time one launch per frame and order instead of one batched launch per order")
-    ap.add_argument("--no-compare", action="store_true", help="plain: skip timing the other launch form")
-    ap.add_argument("--no-mirror", action="store_true", help="plain: skip the mirror-paired comparison")
+    ap.add_argument("--no-compare", action="store_true", help="plain: skip timing the other launch forms")
+    ap.add_argument("--no-mirror", action="store_true",
+                    help="plain: run the step unpaired and skip the mirror-paired per-frame comparison")
     ap.add_argument("--no-peaks", action="store_true",
                     help="plain: skip measuring the device's issue and copy rates (the measured ceilings)")
     ap.add_argument("--no-tune", action="store_true", help="batch: default tilings instead of the autotuner's")
@@ -144,21 +147,44 @@ def bench_plain(args, torch):
     # lists are built here, outside the timed region; workgroups drift out of
     # step, so one tile's staging overlaps another's arithmetic and the
     # frames' tails overlap); --per-frame-step runs B per-frame launches per
-    # order instead.  The other form is timed beside it for comparison.
-    can_batch = info.tiling.tile_x * info.tiling.tile_z * info.tiling.split == 256
+    # order instead.  The step's plan pairs mirror tiles when the geometry
+    # allows it (HODMAS_FLAG_MIRROR: each delay serves a pixel and its mirror
+    # image; the images are the unpaired kernel's up to rounding).  The other
+    # forms are timed beside it for comparison.
+    mplan = None
+    if not args.no_mirror:
+        try:
+            mplan = hodmas.Plan(geom, grid, S, "f32", max_order=max(orders), flags=hodmas.FLAG_MIRROR)
+        except hodmas.HodmasError:
+            mplan = None
+    splan = mplan if mplan is not None else plan
+    sinfo = splan.info()
+    can_batch = all(q.tiling.tile_x * q.tiling.tile_z * q.tiling.split == 256 for q in (info, sinfo))
     batched_step = can_batch and not args.per_frame_step
-    bts = {}
-    if can_batch and (batched_step or not args.no_compare):
+
+    def make_batches(q):
+        qi = q.info()
+        res = {}
         for k in orders:
-            bt = hodmas.Batch(max_frames=args.batch, max_units=info.n_tiles * args.batch,
-                              max_lds_bytes=info.lds_bytes)
-            bt.set([plan] * args.batch, rf_dev, [k] * args.batch, out, stream=stream)
-            bts[k] = bt
+            bt = hodmas.Batch(max_frames=args.batch, max_units=qi.n_tiles * args.batch, max_lds_bytes=qi.lds_bytes)
+            bt.set([q] * args.batch, rf_dev, [k] * args.batch, out, stream=stream)
+            res[k] = bt
+        return res
+
+    bts = make_batches(splan) if can_batch and (batched_step or not args.no_compare) else {}
+    bts_u = (make_batches(plan) if mplan is not None and can_batch and not args.no_compare else bts)
 
     def run_batched(k):
         bts[k].launch(stream=stream)
 
+    def run_batched_unpaired(k):
+        bts_u[k].launch(stream=stream)
+
     def run_per_frame(k):
+        for b in range(args.batch):
+            splan.beamform(rf_dev[b], k, out[b], stream=stream)
+
+    def run_per_frame_unpaired(k):
         for b in range(args.batch):
             plan.beamform(rf_dev[b], k, out[b], stream=stream)
 
@@ -191,8 +217,8 @@ def bench_plain(args, torch):
     value = total_pixch / elapsed / 1e9
     dom = max(orders, key=lambda k: per_order_ms[k])
     achieved = SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
-    dom_kernel = ("hodmas_batch_kernel<%d, f32, %s>" if batched_step else "hodmas_frame_kernel<%d, f32, %s>") % (
-        dom, "comp")
+    dom_kernel = "%s<%d, f32, comp%s>" % ("hodmas_batch_kernel" if batched_step else "hodmas_frame_kernel", dom,
+                                          ", mirror pairs" if mplan is not None else "")
 
     def time_form(run):
         """Per-frame milliseconds of each order when its B frames run through `run`."""
@@ -210,18 +236,28 @@ def bench_plain(args, torch):
             ms[k] = sum(a.elapsed_time(z) for a, z in fev) / (args.steps * args.batch)
         return ms
 
-    # the other launch form of the same step
-    other = None
-    pf_ms = per_order_ms if not batched_step else None
-    if not args.no_compare and can_batch:
-        alt_ms = time_form(run_per_frame if batched_step else run_batched)
-        if batched_step:
-            pf_ms = alt_ms
-        other = {"form": "per-frame launches" if batched_step else "one batched launch per order",
-                 "kernel_us_per_frame": {str(k): round(v * 1e3, 3) for k, v in alt_ms.items()},
-                 "gpixch_s_sum_orders": round(pixch * len(orders) / (sum(alt_ms.values()) * 1e-3) / 1e9, 2),
-                 "headline_speedup": round(sum(alt_ms.values()) / sum(per_order_ms.values()), 3)}
-    for bt in bts.values():
+    # the other launch forms of the same step
+    others = {}
+    pf_ms = per_order_ms if not batched_step and mplan is None else None
+    if not args.no_compare:
+        cand = []
+        if batched_step and mplan is not None:
+            cand.append(("batched_unpaired", "one batched launch per order, unpaired", run_batched_unpaired))
+        if not batched_step and can_batch:
+            cand.append(("batched", "one batched launch per order" + (", mirror pairs" if mplan else ""),
+                         run_batched))
+        if batched_step or mplan is not None:
+            cand.append(("per_frame_unpaired", "per-frame launches, unpaired", run_per_frame_unpaired))
+        for key, desc, run in cand:
+            alt_ms = time_form(run)
+            if key == "per_frame_unpaired":
+                pf_ms = alt_ms
+            others[key] = {"form": desc,
+                           "kernel_us_per_frame": {str(k): round(v * 1e3, 3) for k, v in alt_ms.items()},
+                           "gpixch_s_sum_orders": round(pixch * len(orders) / (sum(alt_ms.values()) * 1e-3) / 1e9,
+                                                        2),
+                           "headline_speedup": round(sum(alt_ms.values()) / sum(per_order_ms.values()), 3)}
+    for bt in set(bts.values()) | set(bts_u.values()):
         bt.close()
 
     # every order 1..kmax from one launch per frame
@@ -250,11 +286,9 @@ def bench_plain(args, torch):
                  "frac": round(f_ach / VALU_PEAK_TSLOT, 4),
                  "traffic": _profiled_traffic("hodmas_orders_kernel<%d, f32, comp>" % kmax)}
 
-    # mirror pairing: the array and the grid are symmetric about x = 0, so one
-    # workgroup forms a tile and its mirror image from one set of delays
-    # (HODMAS_FLAG_MIRROR); tiling per order from the autotuner
+    # mirror pairs as per-frame launches, tiling per order from the autotuner
     mirrored = None
-    if not args.no_mirror:
+    if mplan is not None:
         m_us, m_tiling = {}, {}
         for k in orders:
             t = hodmas.autotune(geom, grid, S, "f32", k, flags=hodmas.FLAG_MIRROR, cache_path=args.tune_cache)
@@ -274,7 +308,8 @@ def bench_plain(args, torch):
             mt = mp.info().tiling
             m_tiling[str(k)] = [mt.tile_x, mt.tile_z, mt.split, mt.chunk]
             mp.close()
-        mirrored = {"kernel": "hodmas_frame_kernel<k, f32, comp, mirror pairs>",
+        mirrored = {"form": "per-frame launches, mirror pairs, autotuned tiling per order",
+                    "kernel": "hodmas_frame_kernel<k, f32, comp, mirror pairs>",
                     "kernel_us_per_frame": {str(k): round(v, 2) for k, v in m_us.items()},
                     "tilings": m_tiling,
                     "speedup_vs_unpaired_per_frame": ({str(k): round(pf_ms[k] * 1e3 / m_us[k], 3) for k in orders}
@@ -336,21 +371,26 @@ def bench_plain(args, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "plain HO-DMAS, 128-element array, 2048 samples/channel, 512x512 grid, "
-                               "FP32 RF, orders 1-6, %d resident frames per step, %s" % (
+                               "FP32 RF, orders 1-6, %d resident frames per step, %s%s" % (
                                    args.batch, "each order one persistent batched launch over the frames"
-                                   if batched_step else "one launch per frame and order"),
+                                   if batched_step else "one launch per frame and order",
+                                   ", mirror pairs" if mplan is not None else ""),
                    "n_elements": n_el, "n_samples": S, "grid": [grid.nx, grid.nz],
-                   "batch_frames": args.batch, "orders": orders,
-                   "tiling": [info.tiling.tile_x, info.tiling.tile_z, info.tiling.split, info.tiling.chunk]},
+                   "batch_frames": args.batch, "orders": orders, "mirror_pairs": mplan is not None,
+                   "tiling": [sinfo.tiling.tile_x, sinfo.tiling.tile_z, sinfo.tiling.split, sinfo.tiling.chunk]},
         "per_order_gpixch_s": per_order,
         "per_order_kernel_us": {str(k): round(per_order_ms[k] * 1e3, 2) for k in orders},
         "fused_all_orders": fused,
-        "other_launch_form": other,
-        "mirror_paired": mirrored,
+        "other_forms": others,
+        "mirror_paired_per_frame": mirrored,
         "roofline": {"bound": "alu", "kernel": dom_kernel,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),
-                     "slots_per_pixch": SLOTS[dom], "traffic": _profiled_traffic(dom_kernel),
+                     "slots_per_pixch": SLOTS[dom],
+                     "slots_model": "the method's slots per pixel-channel (one delay per pixel and element); "
+                                    "mirror pairs share each delay between two pixels, so their kernels "
+                                    "issue fewer" if mplan is not None else "the method's slots per pixel-channel",
+                     "traffic": _profiled_traffic(dom_kernel),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "measured": measured},
         "cpu_baseline": cpu,
@@ -358,6 +398,8 @@ def bench_plain(args, torch):
     }
     print(json.dumps(res))
     plan.close()
+    if mplan is not None:
+        mplan.close()
 
 
 def bench_small(args, torch):

@@ -74,9 +74,10 @@ typedef enum {
 #define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts */
 #define HODMAS_FLAG_CF          0x10u /* weight each pixel by the coherence factor of its
                                          delayed samples (hodmas_beamform only) */
-#define HODMAS_FLAG_MIRROR      0x20u /* hodmas_beamform forms each pixel together with
-                                         its mirror image about x = 0 from one delay
-                                         (symmetric array and grid only, see hodmas_plan) */
+#define HODMAS_FLAG_MIRROR      0x20u /* hodmas_beamform and the batch form each pixel
+                                         together with its mirror image about x = 0 from
+                                         one delay (symmetric array and grid only, see
+                                         hodmas_plan) */
 
 /* Linear array.  element_x_m == NULL means a centred uniform array,
  * x_i = (i - (n_elements-1)/2) * pitch_m.  The pointer is read during
@@ -256,7 +257,8 @@ hodmas_status hodmas_plan_tables(hodmas_plan_t plan, const hodmas_tile_desc** ti
 typedef struct hodmas_batch_s* hodmas_batch_t;
 
 /* Allocate a batch for up to max_frames frames and max_units (frame, tile)
- * units, on the current HIP device.  max_lds_bytes bounds the LDS any member
+ * units (a HODMAS_FLAG_MIRROR plan's units are its n_tiles / 2 mirror pairs),
+ * on the current HIP device.  max_lds_bytes bounds the LDS any member
  * plan may need (0: the largest a workgroup can have); it fixes the persistent
  * grid size.  flags: HODMAS_FLAG_ACC_PLAIN or 0; member plans must match it.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
@@ -267,16 +269,18 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
  * at orders[f] from rf[f] (device) into images[f] (device float32 [nz][nx]).
  * Host arrays of n_frames entries, read during the call.  The work list is
  * copied to the device asynchronously on `stream` (launches on the same stream
- * see it).  Errors: EINVAL (null entries, order outside the plan, plan flags
- * -- including HODMAS_FLAG_CF and HODMAS_FLAG_MIRROR, which the batch
- * kernels do not carry --
- * host-only or other-device plan, too many frames/units, plan LDS above the
- * batch's bound or a workgroup other than 256 threads), EUNSUPPORTED, EDEVICE. */
+ * see it).  A HODMAS_FLAG_MIRROR plan's frame runs as mirror pairs, as in
+ * hodmas_beamform, with the same image bit for bit.  Errors: EINVAL (null
+ * entries, order outside the plan, HODMAS_FLAG_CF -- which the batch kernels
+ * do not carry -- or an accumulation flag other than the batch's, host-only
+ * or other-device plan, too many frames/units, plan LDS above the batch's
+ * bound or a workgroup other than 256 threads), EUNSUPPORTED, EDEVICE. */
 hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
                                const void* const* rf, const int32_t* orders,
                                float* const* images, int32_t n_frames, void* stream);
 
-/* Run the current work list on `stream`: one persistent launch per kind present. */
+/* Run the current work list on `stream`: one persistent launch per kind
+ * present (kind = order x storage type x mirror pairing). */
 hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
 
 /* Build (once) a HIP graph holding the persistent kernels of every kind, with

@@ -1,6 +1,7 @@
 // Batched form: a work list of (frame, tile) units over many frames, grouped by
-// kind (order x storage type) and walked by one persistent kernel per kind;
-// a HIP graph chains the kernels so one graph launch runs the batch.
+// kind (order x storage type x mirror pairing) and walked by one persistent
+// kernel per kind; a HIP graph holds the kernels so one graph launch runs the
+// batch.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -105,26 +106,24 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
         return HODMAS_EDEVICE;
     }
     int max_grid = 0;
-    for (int k = 1; k <= HODMAS_MAX_ORDER; ++k) {
-        for (int dt = 0; dt < 3; ++dt) {
-            const void* fn = hodmas::batch_kernel(k, dt, comp);
-            if (b->lds_bytes > 64 * 1024 &&
-                hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) !=
-                    hipSuccess) {
-                (void)hipGetLastError();
-                delete b;
-                return HODMAS_EUNSUPPORTED;
-            }
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)b->lds_bytes) !=
-                    hipSuccess || per_cu < 1) {
-                (void)hipGetLastError();
-                delete b;
-                return HODMAS_EUNSUPPORTED;
-            }
-            b->grid[hodmas::batch_kind(k, dt)] = per_cu * prop.multiProcessorCount;
-            max_grid = std::max(max_grid, per_cu * prop.multiProcessorCount);
+    for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
+        const void* fn = hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
+                                              hodmas::kind_pairing(kind), comp);
+        if (b->lds_bytes > 64 * 1024 &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return HODMAS_EUNSUPPORTED;
         }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)b->lds_bytes) !=
+                hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            delete b;
+            return HODMAS_EUNSUPPORTED;
+        }
+        b->grid[kind] = per_cu * prop.multiProcessorCount;
+        max_grid = std::max(max_grid, per_cu * prop.multiProcessorCount);
     }
     b->off_frames = align_up(sizeof(BatchHeader));
     b->off_units = b->off_frames + align_up(sizeof(BatchFrame) * (size_t)max_frames);
@@ -167,8 +166,8 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
             const hodmas_plan_s* p = plans[f];
             if (!p || p->magic != hodmas::kPlanMagic || !rf[f] || !images[f])
                 return HODMAS_EINVAL;
-            if ((p->flags & (HODMAS_FLAG_HOST_ONLY | HODMAS_FLAG_CF | HODMAS_FLAG_MIRROR)) || p->device != b->device)
-                return HODMAS_EINVAL;   // no coherence weighting or mirror pairing in the batch kernels
+            if ((p->flags & (HODMAS_FLAG_HOST_ONLY | HODMAS_FLAG_CF)) || p->device != b->device)
+                return HODMAS_EINVAL;   // no coherence weighting in the batch kernels
             if ((p->flags & HODMAS_FLAG_ACC_PLAIN) != (b->flags & HODMAS_FLAG_ACC_PLAIN))
                 return HODMAS_EINVAL;
             if (orders[f] < 1 || orders[f] > p->max_order)
@@ -177,16 +176,22 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
                 return HODMAS_EINVAL;
             if (p->tiling.tile_x * p->tiling.tile_z * p->tiling.split != hodmas::kBlock)
                 return HODMAS_EINVAL;   // the persistent kernels run 256-thread tiles
-            if ((int64_t)(units.size() + p->tiles.size()) > b->max_units)
+            // a mirror plan's units are the pairs: each left-half tile with its mirror
+            const int pairing = (p->flags & HODMAS_FLAG_MIRROR) ? 2 : 1;
+            const int n_units = (int)p->tiles.size() / pairing;
+            const int half = p->grid.nx / p->tiling.tile_x / 2;   // tile columns left of the centre
+            if ((int64_t)units.size() + n_units > b->max_units)
                 return HODMAS_EINVAL;
             pixch += int64_t(p->grid.nx) * p->grid.nz * p->geom.n_elements;
-            for (size_t t = 0; t < p->tiles.size(); ++t) {
+            const int kind = hodmas::batch_kind(orders[f], p->rf.dtype, pairing);
+            for (int i = 0; i < n_units; ++i) {
+                const int t = pairing == 1 ? i : i / half * 2 * half + i % half;
                 const hodmas_tile_desc& td = p->tiles[t];
                 const int64_t pix = int64_t(td.nx) * td.nz;
                 int64_t cost = pix;  // zero-fill only
                 if (td.n_active >= orders[f])
                     cost = td.n_active * (pix * kSlots[orders[f]] + int64_t(td.window) * 2);
-                units.push_back(Unit{cost, hodmas::batch_kind(orders[f], p->rf.dtype), f, (int32_t)t});
+                units.push_back(Unit{cost, kind, f, (int32_t)t});
             }
         }
     } catch (const std::bad_alloc&) {
@@ -247,16 +252,14 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
     const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     const bool comp = !(b->flags & HODMAS_FLAG_ACC_PLAIN);
-    for (int k = 1; k <= HODMAS_MAX_ORDER; ++k) {
-        for (int dt = 0; dt < 3; ++dt) {
-            const int kind = hodmas::batch_kind(k, dt);
-            if (b->end[kind] <= b->begin[kind])
-                continue;
-            const int grid = (int)std::min<int64_t>(b->grid[kind], b->end[kind] - b->begin[kind]);
-            if (hodmas::launch_batch(k, dt, hdr, frames, units, grid, comp, b->lds_bytes, stream) != 0) {
-                (void)hipGetLastError();
-                return HODMAS_EDEVICE;
-            }
+    for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
+        if (b->end[kind] <= b->begin[kind])
+            continue;
+        const int grid = (int)std::min<int64_t>(b->grid[kind], b->end[kind] - b->begin[kind]);
+        if (hodmas::launch_batch(hodmas::kind_order(kind), hodmas::kind_dtype(kind), hodmas::kind_pairing(kind),
+                                 hdr, frames, units, grid, comp, b->lds_bytes, stream) != 0) {
+            (void)hipGetLastError();
+            return HODMAS_EDEVICE;
         }
     }
     return HODMAS_OK;
@@ -272,11 +275,13 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
 // and a present kind gets no more workgroups than it has units.
 namespace {
 
-hipKernelNodeParams node_params(const hodmas_batch_s* b, int order, int dtype, int grid, void** args)
+hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, void** args)
 {
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void*>(hodmas::batch_kernel(order, dtype, !(b->flags & HODMAS_FLAG_ACC_PLAIN)));
+    kp.func = const_cast<void*>(hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
+                                                     hodmas::kind_pairing(kind),
+                                                     !(b->flags & HODMAS_FLAG_ACC_PLAIN)));
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(hodmas::kBlock);
     kp.sharedMemBytes = (unsigned)b->lds_bytes;
@@ -298,16 +303,13 @@ hodmas_status hodmas_batch_capture(hodmas_batch_t b)
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
     bool ok = hipGraphCreate(&b->graph, 0) == hipSuccess;
-    for (int k = 1; k <= HODMAS_MAX_ORDER && ok; ++k) {
-        for (int dt = 0; dt < 3 && ok; ++dt) {
-            const int kind = hodmas::batch_kind(k, dt);
-            const hipKernelNodeParams kp = node_params(b, k, dt, b->grid[kind], args);
-            hipGraphNode_t node = nullptr;
-            ok = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) == hipSuccess;
-            b->node[kind] = node;
-            b->node_grid[kind] = b->grid[kind];
-            b->node_on[kind] = true;
-        }
+    for (int kind = 0; kind < hodmas::kBatchKinds && ok; ++kind) {
+        const hipKernelNodeParams kp = node_params(b, kind, b->grid[kind], args);
+        hipGraphNode_t node = nullptr;
+        ok = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) == hipSuccess;
+        b->node[kind] = node;
+        b->node_grid[kind] = b->grid[kind];
+        b->node_on[kind] = true;
     }
     if (ok)
         ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -345,29 +347,26 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
         }
         b->replay_pending = false;
     }
-    for (int k = 1; k <= HODMAS_MAX_ORDER && change; ++k) {
-        for (int dt = 0; dt < 3; ++dt) {
-            const int kind = hodmas::batch_kind(k, dt);
-            const int n = b->end[kind] - b->begin[kind];
-            const bool on = n > 0;
-            if (on) {
-                const int grid = (int)std::min<int64_t>(b->grid[kind], n);
-                if (grid != b->node_grid[kind]) {
-                    const hipKernelNodeParams kp = node_params(b, k, dt, grid, args);
-                    if (hipGraphExecKernelNodeSetParams(b->exec, b->node[kind], &kp) != hipSuccess) {
-                        (void)hipGetLastError();
-                        return HODMAS_EDEVICE;
-                    }
-                    b->node_grid[kind] = grid;
-                }
-            }
-            if (on != b->node_on[kind]) {
-                if (hipGraphNodeSetEnabled(b->exec, b->node[kind], on ? 1 : 0) != hipSuccess) {
+    for (int kind = 0; kind < hodmas::kBatchKinds && change; ++kind) {
+        const int n = b->end[kind] - b->begin[kind];
+        const bool on = n > 0;
+        if (on) {
+            const int grid = (int)std::min<int64_t>(b->grid[kind], n);
+            if (grid != b->node_grid[kind]) {
+                const hipKernelNodeParams kp = node_params(b, kind, grid, args);
+                if (hipGraphExecKernelNodeSetParams(b->exec, b->node[kind], &kp) != hipSuccess) {
                     (void)hipGetLastError();
                     return HODMAS_EDEVICE;
                 }
-                b->node_on[kind] = on;
+                b->node_grid[kind] = grid;
             }
+        }
+        if (on != b->node_on[kind]) {
+            if (hipGraphNodeSetEnabled(b->exec, b->node[kind], on ? 1 : 0) != hipSuccess) {
+                (void)hipGetLastError();
+                return HODMAS_EDEVICE;
+            }
+            b->node_on[kind] = on;
         }
     }
     if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess ||

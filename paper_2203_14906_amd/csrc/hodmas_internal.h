@@ -40,9 +40,16 @@ struct OrderImages {
 };
 
 // Work list of the persistent batched kernels (device memory).  Units are
-// grouped by kind = (order, storage type); kind k owns units [begin[k], end[k]).
-constexpr int kBatchKinds = HODMAS_MAX_ORDER * 3;
-constexpr int batch_kind(int order, int dtype) { return (order - 1) * 3 + dtype; }
+// grouped by kind = (order, storage type, pixels per delay: 1, or 2 for mirror
+// pairs); kind k owns units [begin[k], end[k]).
+constexpr int kBatchKinds = HODMAS_MAX_ORDER * 3 * 2;
+constexpr int batch_kind(int order, int dtype, int pairing) { return ((order - 1) * 3 + dtype) * 2 + pairing - 1; }
+constexpr int kind_order(int kind) { return kind / 6 + 1; }
+constexpr int kind_dtype(int kind) { return kind / 2 % 3; }
+constexpr int kind_pairing(int kind) { return kind % 2 + 1; }
+static_assert(batch_kind(kind_order(kBatchKinds - 1), kind_dtype(kBatchKinds - 1),
+                         kind_pairing(kBatchKinds - 1)) == kBatchKinds - 1,
+              "kind decoding");
 
 constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
 
@@ -60,6 +67,7 @@ struct BatchFrame {
     int32_t pad[2];
 };
 
+// tile: the tile to form, or for a mirror-pair kind the pair's left tile
 struct BatchUnit {
     int32_t frame;
     int32_t tile;
@@ -109,8 +117,8 @@ int launch_orders(const FrameArgs& a, const OrderImages& out, int kmax, int dtyp
                   int64_t lds_bytes, void* stream);
 
 // The persistent batched kernel of one kind (for graph nodes) and a launch of it.
-const void* batch_kernel(int order, int dtype, bool compensated);
-int launch_batch(int order, int dtype, const BatchHeader* hdr, const BatchFrame* frames,
+const void* batch_kernel(int order, int dtype, int pairing, bool compensated);
+int launch_batch(int order, int dtype, int pairing, const BatchHeader* hdr, const BatchFrame* frames,
                  const BatchUnit* units, int grid, bool compensated, int64_t lds_bytes, void* stream);
 
 }  // namespace hodmas

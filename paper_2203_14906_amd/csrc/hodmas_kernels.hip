@@ -560,19 +560,20 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
     }
 }
 
-// Persistent form: one kernel per (order, storage type).  Its fixed grid walks
-// that kind's slice of the batch's work list -- (frame, tile) units of many
-// frames with their own plans, sorted by estimated cost -- with workgroup b
-// taking units b, 2G-1-b, 2G+b, ... (a snake, which evens out the per-workgroup
-// cost).  Each tile runs exactly the code of the per-frame kernel, so a frame's
+// Persistent form: one kernel per (order, storage type, pairing).  Its fixed
+// grid walks that kind's slice of the batch's work list -- (frame, tile) units
+// of many frames with their own plans, sorted by estimated cost -- with
+// workgroup b taking units b, 2G-1-b, 2G+b, ... (a snake, which evens out the
+// per-workgroup cost).  With M == 2 a unit is a mirror pair, named by its left
+// tile.  Each unit runs exactly the code of the per-frame kernel, so a frame's
 // image does not depend on what else is in the batch.
-template <int K, int DT, bool COMP>
+template <int K, int DT, bool COMP, int M>
 __global__ __launch_bounds__(kMaxBlock) void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr,
                                                               const BatchFrame* __restrict__ frames,
                                                               const BatchUnit* __restrict__ units)
 {
     extern __shared__ float lds[];
-    constexpr int kind = batch_kind(K, DT);
+    constexpr int kind = batch_kind(K, DT, M);
     const BatchHeader h = load_const(hdr, 0);
     const int first = h.begin[kind];
     const int n = h.end[kind] - first;
@@ -583,7 +584,7 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_batch_kernel(const BatchHead
             continue;
         const BatchUnit un = load_const(units, first + u);
         const BatchFrame fr = load_const(frames, un.frame);
-        process_tile<K, DT, COMP>(fr.args, un.tile, lds);
+        process_tile<K, DT, COMP, false, M>(fr.args, un.tile, lds);
     }
 }
 
@@ -960,23 +961,34 @@ int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, boo
     return (int)hipErrorInvalidValue;
 }
 
-template <int K, int DT>
+template <int K, int DT, int M>
 const void* batch_fn(bool comp)
 {
-    return comp ? reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, true>)
-                : reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, false>);
+    return comp ? reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, true, M>)
+                : reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, false, M>);
 }
 
-template <int DT>
+template <int DT, int M>
 const void* batch_fn_dt(int order, bool comp)
 {
     switch (order) {
-    case 1: return batch_fn<1, DT>(comp);
-    case 2: return batch_fn<2, DT>(comp);
-    case 3: return batch_fn<3, DT>(comp);
-    case 4: return batch_fn<4, DT>(comp);
-    case 5: return batch_fn<5, DT>(comp);
-    case 6: return batch_fn<6, DT>(comp);
+    case 1: return batch_fn<1, DT, M>(comp);
+    case 2: return batch_fn<2, DT, M>(comp);
+    case 3: return batch_fn<3, DT, M>(comp);
+    case 4: return batch_fn<4, DT, M>(comp);
+    case 5: return batch_fn<5, DT, M>(comp);
+    case 6: return batch_fn<6, DT, M>(comp);
+    }
+    return nullptr;
+}
+
+template <int M>
+const void* batch_fn_m(int order, int dtype, bool comp)
+{
+    switch (dtype) {
+    case HODMAS_F32: return batch_fn_dt<HODMAS_F32, M>(order, comp);
+    case HODMAS_F16: return batch_fn_dt<HODMAS_F16, M>(order, comp);
+    case HODMAS_I16: return batch_fn_dt<HODMAS_I16, M>(order, comp);
     }
     return nullptr;
 }
@@ -993,20 +1005,19 @@ int launch_orders(const FrameArgs& a, const OrderImages& out, int kmax, int dtyp
     return (int)hipErrorInvalidValue;
 }
 
-const void* batch_kernel(int order, int dtype, bool compensated)
+const void* batch_kernel(int order, int dtype, int pairing, bool compensated)
 {
-    switch (dtype) {
-    case HODMAS_F32: return batch_fn_dt<HODMAS_F32>(order, compensated);
-    case HODMAS_F16: return batch_fn_dt<HODMAS_F16>(order, compensated);
-    case HODMAS_I16: return batch_fn_dt<HODMAS_I16>(order, compensated);
+    switch (pairing) {
+    case 1: return batch_fn_m<1>(order, dtype, compensated);
+    case 2: return batch_fn_m<2>(order, dtype, compensated);
     }
     return nullptr;
 }
 
-int launch_batch(int order, int dtype, const BatchHeader* hdr, const BatchFrame* frames,
+int launch_batch(int order, int dtype, int pairing, const BatchHeader* hdr, const BatchFrame* frames,
                  const BatchUnit* units, int grid, bool compensated, int64_t lds_bytes, void* stream)
 {
-    const void* fn = batch_kernel(order, dtype, compensated);
+    const void* fn = batch_kernel(order, dtype, pairing, compensated);
     if (!fn)
         return (int)hipErrorInvalidValue;
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};

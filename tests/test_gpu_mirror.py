@@ -4,7 +4,7 @@ the FP64 oracle to the same bars as the unpaired kernel (relative L2 1e-5 for
 FP32 storage, 2e-5 on the same stored values for FP16 / int16) and against the
 unpaired launch (rounding-level differences only), over ragged grids, several
 tilings, multi-chunk staging, record-boundary checks, coherence weighting and
-odd and even element counts."""
+odd and even element counts -- per frame and as pair units in the batch."""
 import sys
 
 import numpy as np
@@ -12,6 +12,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2203_14906_amd import phantom as ph
+from sign_band import band_rel_l2
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -146,8 +147,7 @@ def test_mirror_symmetric_input_gives_symmetric_image(hd):
 
 
 def test_mirror_plan_in_other_entry_points(hd):
-    """The all-orders pass runs a mirror plan unpaired (same images); the batch
-    refuses it."""
+    """The all-orders pass runs a mirror plan unpaired (same images)."""
     f = ph.config_frame(1)
     arr = ph.to_fp32(f.rf)
     dev = torch.from_numpy(arr).cuda()
@@ -158,11 +158,88 @@ def test_mirror_plan_in_other_entry_points(hd):
         err = rel_l2(imgs[k - 1].cpu().numpy().astype(np.float64), o)
         say("mirror plan, all-orders pass k=%d rel L2 %.2e" % (k, err))
         assert err <= 1e-5
-    info = plan.info()
-    bt = hd.Batch(max_frames=1, max_units=info.n_tiles, max_lds_bytes=64 * 1024)
-    out = torch.empty((f.grid.nz, f.grid.nx), dtype=torch.float32, device="cuda")
-    with pytest.raises(hd.HodmasError) as ei:
-        bt.set([plan], [dev], [1], [out])
-    assert ei.value.status == hd.EINVAL
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "i16"])
+def test_mirror_pairs_in_the_batch(hd, dtype):
+    """Mirror plans in a batch run as pair units of their own kinds, mixed with
+    unpaired plans of the same and other orders: every image equals the
+    frame's own hodmas_beamform launch bit for bit (direct launch and graph
+    replays), and the mirror images match the oracle."""
+    grid = symmetric_grid(64, 53, 0.17e-3, 0.2e-3, 0.21e-3)
+    frames, plans, devs, orders, scales = [], [], [], [], []
+    for i, (n_elem, flags, k) in enumerate([(16, hd.FLAG_MIRROR, 6), (13, hd.FLAG_MIRROR, 3), (16, 0, 6),
+                                            (13, hd.FLAG_MIRROR, 1), (16, hd.FLAG_MIRROR, 6), (13, 0, 2)]):
+        f = ph.make_frame(n_elem, 300, 64, 53, n_points=6, n_lines=1, snr_db=15.0, seed=40 + i)
+        arr, scale = stored(f.rf, dtype, seed=40 + i)
+        plans.append(hd.Plan(f.geometry, grid, 300, dtype, max_order=6, dequant_scale=scale, flags=flags,
+                             tiling=(16, 16, 1, 8) if i == 4 else None))
+        frames.append((f, arr))
+        devs.append(torch.from_numpy(np.ascontiguousarray(arr)).cuda())
+        orders.append(k)
+        scales.append(scale)
+    ref = [p.beamform(d, k).cpu().numpy() for p, d, k in zip(plans, devs, orders)]
+    lds = max(p.info().lds_bytes for p in plans)
+    units = sum(p.info().n_tiles for p in plans)
+    bt = hd.Batch(max_frames=len(plans), max_units=units, max_lds_bytes=lds)
+    outs = [torch.full((grid.nz, grid.nx), float("nan"), dtype=torch.float32, device="cuda") for _ in plans]
+    bt.set(plans, devs, orders, outs)
+    paired = sum(p.info().n_tiles // (2 if p.info().flags & hd.FLAG_MIRROR else 1) for p in plans)
+    assert bt.info().n_units == paired
+    bt.launch()
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), ref[i]), "frame %d differs from its own launch" % i
+    bt.capture()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        bt.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), ref[i]), "replay %d frame %d" % (rep, i)
+    # this frame set holds sign-change pixels (frame 0: a sample 5e-9 from zero,
+    # where one float32 delay ulp moves e_6 by ten percent), so the error is
+    # taken from the oracle's delay-uncertainty band there
+    for i, (p, (f, arr)) in enumerate(zip(plans, frames)):
+        err, flagged = band_rel_l2(ref[i], arr, f.geometry, grid, orders[i],
+                                   dequant_scale=scales[i] if dtype == "i16" else None)
+        say("batch %s frame %d mirror %d k=%d rel L2 from the band %.2e (%d sign-change pixels)"
+            % (dtype, i, bool(p.info().flags & hd.FLAG_MIRROR), orders[i], err, flagged))
+        assert err <= TOL[dtype]
+    bt.close()
+    for p in plans:
+        p.close()
+
+
+def test_mirror_batch_config2_matches_oracle_samples(hd):
+    """Config 2 as the bench's step runs it: eight frames of mirror plans in one
+    batched launch per order; each image equals its own paired launch bit for
+    bit, and sampled pixels match the oracle."""
+    p = ph.CONFIGS[2]
+    fr = [ph.make_frame(p["n_elements"], p["n_samples"], p["nx"], p["nz"], n_points=p["n_points"],
+                        n_lines=p["n_lines"], snr_db=p["snr_db"], seed=2000 + b) for b in range(2)]
+    grid = fr[0].grid
+    plan = hd.Plan(fr[0].geometry, grid, p["n_samples"], "f32", max_order=6, flags=hd.FLAG_MIRROR)
+    devs = [torch.from_numpy(ph.to_fp32(f.rf)).cuda() for f in fr] * 4
+    bt = hd.Batch(max_frames=8, max_units=8 * plan.info().n_tiles, max_lds_bytes=plan.info().lds_bytes)
+    outs = [torch.empty((grid.nz, grid.nx), dtype=torch.float32, device="cuda") for _ in range(8)]
+    rng = np.random.default_rng(7)
+    # both halves of the image, the centre columns and the corners
+    ix = np.concatenate([rng.integers(0, grid.nx, 40), [0, grid.nx - 1, grid.nx // 2 - 1, grid.nx // 2]])
+    iz = np.concatenate([rng.integers(0, grid.nz, 40), [0, grid.nz - 1, 0, grid.nz - 1]])
+    for k in (1, 3, 6):
+        bt.set([plan] * 8, devs, [k] * 8, outs)
+        bt.launch()
+        own = [plan.beamform(devs[j], k).cpu().numpy() for j in range(2)]
+        for j, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), own[j % 2])
+        arr = ph.to_fp32(fr[0].rf)
+        ref = O.beamform(arr, fr[0].geometry, grid, k, pixels=(ix, iz))
+        got = own[0][iz, ix].astype(np.float64)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        say("config 2 mirror batch k=%d sampled rel L2 %.2e" % (k, err))
+        assert err <= 1e-5
     bt.close()
     plan.close()
