@@ -70,6 +70,11 @@ template <> struct Storage<HODMAS_F32> { using T = float; };
 template <> struct Storage<HODMAS_F16> { using T = _Float16; };
 template <> struct Storage<HODMAS_I16> { using T = short; };
 
+// Word 3 of a raw (stride 0) buffer resource on gfx950: 32-bit data format,
+// no swizzle; with stride 0 an access is in range iff its byte offset is below
+// the resource's size.
+constexpr int kBufferFlags = 0x00020000;
+
 __device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ float widen(_Float16 v) { return (float)v; }
 __device__ __forceinline__ float widen(short v) { return (float)v; }
@@ -191,19 +196,24 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
                                             float* __restrict__ lds, int wave, int nwaves, int lane)
 {
     using T = typename Storage<DT>::T;
-    const Global<const T> rf = global_ptr(static_cast<const T*>(A.rf));
+    constexpr int esz = int(sizeof(T));
     // Each wave stages a contiguous run of rows; lanes run along the window.
     // Latency, not bandwidth, sets the cost here: one vector load brings 64
     // rows' table entries (lane j holds row j), then the sample loads go out
-    // kInFlight at a time before any wait, their addresses read out of the
-    // entry lanes.  Every load address is clamped in bounds (row to the
-    // chunk, sample to the record); out-of-range lanes store zero.
+    // kInFlight at a time before any wait.  Each row is read through a buffer
+    // resource spanning exactly its channel's record, built in scalar
+    // registers from the entry lanes: a sample index outside [0, S) -- before
+    // the record, past its end, or negative -- is out of the resource's range
+    // and loads as zero in hardware, so no lane clamps or selects.
     constexpr int kInFlight = 16;
     const int rows = M * nch;
     const int per_wave = (rows + nwaves - 1) / nwaves;
     const int s0 = wave * per_wave;
     const int s1 = min(rows, s0 + per_wave);
     const Global<const int> ent = global_ptr(reinterpret_cast<const int*>(st));
+    const char* rf = static_cast<const char*>(A.rf);
+    const int64_t row_bytes = int64_t(A.stride) * esz;
+    const int record_bytes = A.n_samples * esz;
     for (int c = s0; c < s1; c += 64) {
         const int j = min(c + lane, s1 - 1);
         const bool mirrored = M == 2 && j >= nch;
@@ -219,15 +229,21 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
 #pragma unroll
                 for (int m = 0; m < kInFlight; ++m) {
                     const int ch = __builtin_amdgcn_readlane(my_channel, m0 + m);
-                    const int t = __builtin_amdgcn_readlane(my_first, m0 + m) + i;
-                    const int tc = min(max(t, 0), A.n_samples - 1);
-                    const float x = widen(rf[(int64_t)ch * A.stride + tc]) * A.in_scale;
-                    v[m] = (m0 + m < cend && i < window && t == tc) ? x : 0.f;
+                    const int first = __builtin_amdgcn_readlane(my_first, m0 + m);
+                    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                        const_cast<char*>(rf + ch * row_bytes), (short)0, record_bytes, kBufferFlags);
+                    const int off = (first + i) * esz;
+                    if constexpr (DT == HODMAS_F32)
+                        v[m] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+                    else if constexpr (DT == HODMAS_F16)
+                        v[m] = (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0));
+                    else
+                        v[m] = (float)(short)__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
                 }
 #pragma unroll
                 for (int m = 0; m < kInFlight; ++m)
                     if (m0 + m < cend && i < window)
-                        lds[(c + m0 + m) * window + i] = v[m];
+                        lds[(c + m0 + m) * window + i] = v[m] * A.in_scale;
             }
         }
     }
