@@ -346,8 +346,12 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         return HODMAS_EUNSUPPORTED;
     }
     if (int64_t(p->tiling.chunk) * p->max_window * 4 * rows > cap) {
-        int c = (int)std::max<int64_t>(1, cap / (int64_t(p->max_window) * 4 * rows));
-        p->tiling.chunk = c;
+        const int c = (int)std::max<int64_t>(1, cap / (int64_t(p->max_window) * 4 * rows));
+        // as many chunks as the cap needs, of equal size: no short last chunk
+        // pays a full staging round, and the smaller LDS footprint can keep
+        // more workgroups on a CU
+        const int n_chunks = (int)ceil_div(p->tiling.chunk, c);
+        p->tiling.chunk = (int)ceil_div(p->tiling.chunk, n_chunks);
         st = build_tables(p);  // entry offsets depend on the chunk
         if (st != HODMAS_OK) {
             delete p;

@@ -247,8 +247,31 @@ def test_mirror_lds_holds_both_rows():
     assert b.max_window == a.max_window
     assert b.lds_bytes == 2 * b.tiling.chunk * b.max_window * 4 <= 40 * 1024
     assert b.tiling.chunk <= a.tiling.chunk
+    # the automatic chunk splits the 128 elements into equal chunks
+    assert b.tiling.chunk == 64
     plain.close()
     mir.close()
+
+
+def test_automatic_chunks_are_balanced():
+    """When the LDS cap needs several chunks, they are of equal size (the last
+    one at most one element short), and no more of them than the cap needs."""
+    for n, S in ((128, 2048), (192, 2048), (256, 2048), (100, 1500)):
+        g = ph.Geometry(n)
+        w, d = ph.field_of_view(n, S)
+        for nx, flags in ((256, 0), (256, hodmas.FLAG_MIRROR), (64, 0)):
+            grid = ph.make_grid(nx, nx, w, d)
+            p = _plan(g, grid, S, flags=flags)
+            inf = p.info()
+            rows = 2 if flags else 1
+            c, win = inf.tiling.chunk, inf.max_window
+            n_chunks = -(-n // c)
+            assert inf.lds_bytes >= c * win * 4 * rows
+            assert c * win * 4 * rows <= 40 * 1024
+            assert n - (n_chunks - 1) * c >= c - n_chunks       # last chunk nearly full
+            largest = max(1, 40 * 1024 // (win * 4 * rows))
+            assert n_chunks == -(-n // min(n, largest))         # no more chunks than the cap needs
+            p.close()
 
 
 @pytest.mark.parametrize("n_elem,tiling", [(24, (16, 16, 1, 8)), (13, (8, 8, 4, 3)), (32, (16, 8, 2, 0))])
