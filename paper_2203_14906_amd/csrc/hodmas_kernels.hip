@@ -583,10 +583,16 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 // per-workgroup cost).  With M == 2 a unit is a mirror pair, named by its left
 // tile.  Each unit runs exactly the code of the per-frame kernel, so a frame's
 // image does not depend on what else is in the batch.
+// Mirror pairs keep two pixels' sums per lane; from order 4 on that would take
+// a paired kernel above 80 VGPRs (4-5 waves per SIMD), while a 64-element
+// chunk's LDS leaves room for six workgroups per CU.  Asking for six waves
+// costs a few spills per staged chunk, none in the element loop.
+constexpr int batch_min_waves(int K, int M) { return M == 2 && K >= 4 ? 6 : 1; }
+
 template <int K, int DT, bool COMP, int M>
-__global__ __launch_bounds__(kMaxBlock) void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr,
-                                                              const BatchFrame* __restrict__ frames,
-                                                              const BatchUnit* __restrict__ units)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_min_waves(K, M))))
+void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr, const BatchFrame* __restrict__ frames,
+                         const BatchUnit* __restrict__ units)
 {
     extern __shared__ float lds[];
     constexpr int kind = batch_kind(K, DT, M);
