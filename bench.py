@@ -70,7 +70,7 @@ def parse():
                     help="plain: time one launch per frame and order instead of one batched launch per order")
     ap.add_argument("--no-compare", action="store_true", help="plain: skip timing the other launch forms")
     ap.add_argument("--no-mirror", action="store_true",
-                    help="plain: run the step unpaired and skip the mirror-paired per-frame comparison")
+                    help="plain and batch: no mirror pairs (plain: also skip the per-frame paired comparison)")
     ap.add_argument("--no-peaks", action="store_true",
                     help="plain: skip measuring the device's issue and copy rates (the measured ceilings)")
     ap.add_argument("--no-tune", action="store_true", help="batch: default tilings instead of the autotuner's")
@@ -531,11 +531,13 @@ def bench_reduced(args, torch):
     print(json.dumps(res))
 
 
-def _mixed_frames(torch, specs, with_fp32, tune_cache=None):
+def _mixed_frames(torch, specs, with_fp32, tune_cache=None, mirror=False):
     """Device-resident frames of the mixed workload; the RF of each (N, S)
     shape comes from one seeded phantom shared by the frames of that shape.
     With ``tune_cache`` the FP16 plans take the autotuner's tiling (tuned at
-    order 6 among the tilings a batch accepts, cached in that file)."""
+    order 6 among the tilings a batch accepts, cached in that file).  With
+    ``mirror`` the FP16 plans pair mirror tiles (the arrays are centred and the
+    grids symmetric about x = 0); the FP32 plans stay unpaired."""
     from paper_2203_14906_amd import hodmas, phantom as ph
     rf_cache, plans, frames = {}, {}, []
     for sp in specs:
@@ -549,10 +551,11 @@ def _mixed_frames(torch, specs, with_fp32, tune_cache=None):
             grid = ph.make_grid(side, side, w, d)
             geom = ph.Geometry(n)
             tiling = None
+            pflags = hodmas.FLAG_MIRROR if mirror else 0
             if tune_cache is not None:
-                tiling = hodmas.autotune(geom, grid, S, "f16", 6, flags=hodmas.FLAG_TUNE_BATCH,
+                tiling = hodmas.autotune(geom, grid, S, "f16", 6, flags=hodmas.FLAG_TUNE_BATCH | pflags,
                                          cache_path=tune_cache)
-            plans[(n, S, side)] = (hodmas.Plan(geom, grid, S, "f16", max_order=6, tiling=tiling),
+            plans[(n, S, side)] = (hodmas.Plan(geom, grid, S, "f16", max_order=6, tiling=tiling, flags=pflags),
                                    hodmas.Plan(geom, grid, S, "f32", max_order=6) if with_fp32 else None)
         frames.append(dict(spec=sp, rf16=rf_cache[(n, S)][0], rf32=rf_cache[(n, S)][1],
                            plan16=plans[(n, S, side)][0], plan32=plans[(n, S, side)][1],
@@ -562,15 +565,15 @@ def _mixed_frames(torch, specs, with_fp32, tune_cache=None):
 
 def bench_batch(args, torch):
     """256 mixed frames (N, S, grid side, order drawn per frame; FP16 RF) in one
-    persistent launch replayed from a HIP graph, against 256 plain per-frame
-    FP32 launches on one stream.  All frames are submitted at t = 0; latency is
+    persistent launch replayed from a HIP graph, with mirror pairs (--no-mirror:
+    unpaired), against 256 plain per-frame FP32 launches on one stream.  All frames are submitted at t = 0; latency is
     each frame's completion time."""
     import numpy as np
     from paper_2203_14906_amd import hodmas, phantom as ph
     specs = ph.mixed_batch_specs(256, seed=4000)
     t_tune = time.perf_counter()
     frames, plans = _mixed_frames(torch, specs, with_fp32=True,
-                                  tune_cache=None if args.no_tune else args.tune_cache)
+                                  tune_cache=None if args.no_tune else args.tune_cache, mirror=not args.no_mirror)
     t_tune = time.perf_counter() - t_tune
     outs_b = [torch.empty((f["spec"]["side"],) * 2, dtype=torch.float32, device="cuda") for f in frames]
     outs_p = [torch.empty_like(o) for o in outs_b]
@@ -618,6 +621,7 @@ def bench_batch(args, torch):
                                   "grid side in {256,512,768,1024}, order 1..6, seed 4000",
                       "units": inf.n_units, "grid": inf.grid, "lds_bytes": inf.lds_bytes,
                       "tilings": "autotuned" if not args.no_tune else "default",
+                      "mirror_pairs": not args.no_mirror,
                       "setup_s_incl_tuning": round(t_tune, 1)},
            "batched": {"frames_per_s": round(256 / (tb_ms * 1e-3), 1), "batch_ms": round(tb_ms, 3),
                        "p50_ms": round(tb_ms, 3), "p99_ms": round(tb_ms, 3),

@@ -35,7 +35,12 @@ struct hodmas_batch_s {
     int64_t max_units = 0;
     int64_t lds_bytes = 0;
     uint32_t flags = 0;
-    int grid[hodmas::kBatchKinds] = {};   // persistent workgroups per kind
+    int cus = 0;                          // compute units of the device
+    int grid[hodmas::kBatchKinds] = {};   // persistent workgroups per kind at lds_bytes
+    // the current work list's kinds: LDS of their largest member plan and the
+    // persistent grid that LDS allows
+    int64_t kind_lds[hodmas::kBatchKinds] = {};
+    int kind_grid[hodmas::kBatchKinds] = {};
     size_t off_frames = 0, off_units = 0, bytes = 0;
     char* d_buf = nullptr;
     char* h_buf = nullptr;           // pinned staging of the work list
@@ -47,6 +52,7 @@ struct hodmas_batch_s {
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node[hodmas::kBatchKinds] = {};   // one kernel node per kind
     int node_grid[hodmas::kBatchKinds] = {};         // its current grid in `exec`
+    int64_t node_lds[hodmas::kBatchKinds] = {};      // and its dynamic LDS
     bool node_on[hodmas::kBatchKinds] = {};          // enabled in `exec`
     hipEvent_t replayed = nullptr;   // the last replay's completion
     bool replay_pending = false;
@@ -125,6 +131,7 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
         b->grid[kind] = per_cu * prop.multiProcessorCount;
         max_grid = std::max(max_grid, per_cu * prop.multiProcessorCount);
     }
+    b->cus = prop.multiProcessorCount;
     b->off_frames = align_up(sizeof(BatchHeader));
     b->off_units = b->off_frames + align_up(sizeof(BatchFrame) * (size_t)max_frames);
     b->bytes = b->off_units + align_up(sizeof(BatchUnit) * (size_t)max_units);
@@ -161,6 +168,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
     };
     std::vector<Unit> units;
     int64_t pixch = 0;
+    int64_t kl[hodmas::kBatchKinds] = {};   // LDS each kind's largest plan needs
     try {
         for (int32_t f = 0; f < n_frames; ++f) {
             const hodmas_plan_s* p = plans[f];
@@ -184,6 +192,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
                 return HODMAS_EINVAL;
             pixch += int64_t(p->grid.nx) * p->grid.nz * p->geom.n_elements;
             const int kind = hodmas::batch_kind(orders[f], p->rf.dtype, pairing);
+            kl[kind] = std::max(kl[kind], p->lds_bytes);
             for (int i = 0; i < n_units; ++i) {
                 const int t = pairing == 1 ? i : i / half * 2 * half + i % half;
                 const hodmas_tile_desc& td = p->tiles[t];
@@ -196,6 +205,24 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
         }
     } catch (const std::bad_alloc&) {
         return HODMAS_ENOMEM;
+    }
+    // Each kind runs with the LDS its own plans need, and as many persistent
+    // workgroups as that LDS lets a CU hold: one large-LDS plan no longer
+    // holds every other kind to its occupancy.
+    int kg[hodmas::kBatchKinds] = {};
+    const bool comp = !(b->flags & HODMAS_FLAG_ACC_PLAIN);
+    for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
+        if (kl[kind] == 0)
+            continue;
+        const void* fn = hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
+                                              hodmas::kind_pairing(kind), comp);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)kl[kind]) !=
+                hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            return HODMAS_EDEVICE;
+        }
+        kg[kind] = per_cu * b->cus;
     }
     // grouped by kind (one persistent kernel each), heaviest units first within a kind
     std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) {
@@ -221,6 +248,8 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
     }
     std::memcpy(b->begin, hdr->begin, sizeof(b->begin));
     std::memcpy(b->end, hdr->end, sizeof(b->end));
+    std::memcpy(b->kind_lds, kl, sizeof(kl));
+    std::memcpy(b->kind_grid, kg, sizeof(kg));
     for (int32_t f = 0; f < n_frames; ++f) {
         std::memset(&frames[f], 0, sizeof(BatchFrame));
         frames[f].args = hodmas::frame_args(plans[f], rf[f], images[f]);
@@ -241,6 +270,8 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
     b->info.n_frames = n_frames;
     b->info.n_units = (int64_t)units.size();
     b->info.pixel_channels = pixch;
+    b->info.grid = *std::max_element(kg, kg + hodmas::kBatchKinds);
+    b->info.lds_bytes = *std::max_element(kl, kl + hodmas::kBatchKinds);
     return HODMAS_OK;
 }
 
@@ -255,9 +286,9 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
     for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
         if (b->end[kind] <= b->begin[kind])
             continue;
-        const int grid = (int)std::min<int64_t>(b->grid[kind], b->end[kind] - b->begin[kind]);
+        const int grid = (int)std::min<int64_t>(b->kind_grid[kind], b->end[kind] - b->begin[kind]);
         if (hodmas::launch_batch(hodmas::kind_order(kind), hodmas::kind_dtype(kind), hodmas::kind_pairing(kind),
-                                 hdr, frames, units, grid, comp, b->lds_bytes, stream) != 0) {
+                                 hdr, frames, units, grid, comp, b->kind_lds[kind], stream) != 0) {
             (void)hipGetLastError();
             return HODMAS_EDEVICE;
         }
@@ -272,10 +303,11 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
 // each replay the nodes are fitted to the current work list in the
 // instantiated graph itself: a kind that is absent is switched off (a
 // persistent grid that only finds nothing to do still costs microseconds),
-// and a present kind gets no more workgroups than it has units.
+// and a present kind runs with the LDS its own plans need and the persistent
+// grid that LDS allows, cut to its unit count.
 namespace {
 
-hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, void** args)
+hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, int64_t lds, void** args)
 {
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
@@ -284,7 +316,7 @@ hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, voi
                                                      !(b->flags & HODMAS_FLAG_ACC_PLAIN)));
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(hodmas::kBlock);
-    kp.sharedMemBytes = (unsigned)b->lds_bytes;
+    kp.sharedMemBytes = (unsigned)lds;
     kp.kernelParams = args;
     kp.extra = nullptr;
     return kp;
@@ -304,11 +336,12 @@ hodmas_status hodmas_batch_capture(hodmas_batch_t b)
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
     bool ok = hipGraphCreate(&b->graph, 0) == hipSuccess;
     for (int kind = 0; kind < hodmas::kBatchKinds && ok; ++kind) {
-        const hipKernelNodeParams kp = node_params(b, kind, b->grid[kind], args);
+        const hipKernelNodeParams kp = node_params(b, kind, b->grid[kind], b->lds_bytes, args);
         hipGraphNode_t node = nullptr;
         ok = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) == hipSuccess;
         b->node[kind] = node;
         b->node_grid[kind] = b->grid[kind];
+        b->node_lds[kind] = b->lds_bytes;
         b->node_on[kind] = true;
     }
     if (ok)
@@ -338,7 +371,8 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
     for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
         const int n = b->end[kind] - b->begin[kind];
         change = change || (n > 0) != b->node_on[kind] ||
-                 (n > 0 && (int)std::min<int64_t>(b->grid[kind], n) != b->node_grid[kind]);
+                 (n > 0 && ((int)std::min<int64_t>(b->kind_grid[kind], n) != b->node_grid[kind] ||
+                            b->kind_lds[kind] != b->node_lds[kind]));
     }
     if (change && b->replay_pending) {
         if (hipEventSynchronize(b->replayed) != hipSuccess) {
@@ -351,14 +385,15 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
         const int n = b->end[kind] - b->begin[kind];
         const bool on = n > 0;
         if (on) {
-            const int grid = (int)std::min<int64_t>(b->grid[kind], n);
-            if (grid != b->node_grid[kind]) {
-                const hipKernelNodeParams kp = node_params(b, kind, grid, args);
+            const int grid = (int)std::min<int64_t>(b->kind_grid[kind], n);
+            if (grid != b->node_grid[kind] || b->kind_lds[kind] != b->node_lds[kind]) {
+                const hipKernelNodeParams kp = node_params(b, kind, grid, b->kind_lds[kind], args);
                 if (hipGraphExecKernelNodeSetParams(b->exec, b->node[kind], &kp) != hipSuccess) {
                     (void)hipGetLastError();
                     return HODMAS_EDEVICE;
                 }
                 b->node_grid[kind] = grid;
+                b->node_lds[kind] = b->kind_lds[kind];
             }
         }
         if (on != b->node_on[kind]) {

@@ -215,3 +215,47 @@ def test_batch_rejects_bad_work_lists(hd):
         x.close()
     for x in (p4, plain, host):
         x.close()
+
+
+def test_each_kind_gets_its_own_lds_and_grid(hd):
+    """A kind runs with the LDS of its own largest plan, so a small-LDS work
+    list gets a larger persistent grid than a large-LDS one in the same batch;
+    graph replays refit the nodes' LDS and grid when the list changes, and
+    every image stays bitwise its own launch."""
+    f = ph.config_frame(1)
+    arr = ph.to_fp32(f.rf)
+    dev = torch.from_numpy(arr).cuda()
+    S = arr.shape[1]
+    big = hd.Plan(f.geometry, f.grid, S, "f32", max_order=4, tiling=(16, 16, 1, 64))
+    small = hd.Plan(f.geometry, f.grid, S, "f32", max_order=4, tiling=(16, 16, 1, 4))
+    lb, ls = big.info().lds_bytes, small.info().lds_bytes
+    assert ls < lb
+    bt = hd.Batch(max_frames=4, max_units=4 * big.info().n_tiles, max_lds_bytes=64 * 1024)
+    outs = [torch.full((f.grid.nz, f.grid.nx), float("nan"), dtype=torch.float32, device="cuda")
+            for _ in range(4)]
+    ref = {(id(p), k): p.beamform(dev, k).cpu().numpy() for p in (big, small) for k in (2, 4)}
+    captured = False
+    for rep, plan in enumerate([big, small, big, small]):
+        for o in outs:
+            o.fill_(float("nan"))
+        bt.set([plan] * 4, [dev] * 4, [2, 4, 2, 4], outs)
+        inf = bt.info()
+        assert inf.lds_bytes == plan.info().lds_bytes
+        if plan is small:
+            grid_small = inf.grid
+        else:
+            grid_big = inf.grid
+        if not captured:
+            bt.launch()
+            bt.capture()
+            captured = True
+        else:
+            bt.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), ref[(id(plan), [2, 4][i % 2])]), (rep, i)
+    say("per-kind LDS: big %d B -> grid %d, small %d B -> grid %d" % (lb, grid_big, ls, grid_small))
+    assert grid_small >= grid_big
+    bt.close()
+    big.close()
+    small.close()
