@@ -56,3 +56,30 @@ def test_autotune_mirror_pairs(tmp_path):
     ref = O.beamform(arr, f.geometry, f.grid, 2)
     assert np.linalg.norm(img - ref) / np.linalg.norm(ref) <= 1e-5
     plan.close()
+
+
+def test_autotune_batch_mirror_pairs(tmp_path):
+    """HODMAS_FLAG_TUNE_BATCH | HODMAS_FLAG_MIRROR (the mixed batch's tuning):
+    a 256-thread tiling the pairing accepts; a batch of the tuned paired plan
+    gives the plan's own images bit for bit."""
+    assert torch.cuda.is_available()
+    from paper_2203_14906_amd import hodmas
+    f = ph.config_frame(1)
+    cache = str(tmp_path / "tune.jsonl")
+    til = hodmas.autotune(f.geometry, f.grid, 1024, "f16", 6,
+                          flags=hodmas.FLAG_TUNE_BATCH | hodmas.FLAG_MIRROR, cache_path=cache)
+    tx, tz, split, _ = til
+    assert tx * tz * split == 256
+    assert f.grid.nx % tx == 0 and (f.grid.nx // tx) % 2 == 0
+    plan = hodmas.Plan(f.geometry, f.grid, 1024, "f16", max_order=6, tiling=til, flags=hodmas.FLAG_MIRROR)
+    rf = torch.from_numpy(ph.to_fp16(f.rf)).cuda()
+    own = [plan.beamform(rf, k).cpu().numpy() for k in (1, 6)]
+    bt = hodmas.Batch(max_frames=2, max_units=2 * plan.info().n_tiles, max_lds_bytes=plan.info().lds_bytes)
+    outs = [torch.empty((f.grid.nz, f.grid.nx), dtype=torch.float32, device="cuda") for _ in range(2)]
+    bt.set([plan, plan], [rf, rf], [1, 6], outs)
+    bt.launch()
+    torch.cuda.synchronize()
+    for o, ref in zip(outs, own):
+        assert np.array_equal(o.cpu().numpy(), ref)
+    bt.close()
+    plan.close()
