@@ -408,7 +408,7 @@ def bench_small(args, torch):
     overhead: report single-launch latency (host wall clock of launch plus
     synchronize, and the kernel's own time from HIP events) and throughput over
     1024 back-to-back frames, as per-frame launches and as one persistent batch
-    launch replayed from a HIP graph."""
+    launch replayed from a HIP graph (unpaired and with mirror pairs)."""
     from paper_2203_14906_amd import hodmas, phantom as ph
     dev = torch.device("cuda:0")
     p = ph.CONFIGS[1]
@@ -429,6 +429,26 @@ def bench_small(args, torch):
                       "n_tiles": info.n_tiles, "frames_back_to_back": n_frames},
            "per_order": {}}
     bt = hodmas.Batch(max_frames=n_frames, max_units=info.n_tiles * n_frames, max_lds_bytes=info.lds_bytes)
+    # the batched form again with mirror pairs (the array and grid are symmetric)
+    mplan = btm = None
+    if not args.no_mirror:
+        mplan = hodmas.Plan(geom, grid, p["n_samples"], "f32", max_order=max(orders), flags=hodmas.FLAG_MIRROR)
+        mi = mplan.info()
+        btm = hodmas.Batch(max_frames=n_frames, max_units=mi.n_tiles * n_frames, max_lds_bytes=mi.lds_bytes)
+
+    def time_replays(b):
+        b.capture()
+        for _ in range(2):
+            b.replay(stream=stream)
+        torch.cuda.synchronize()
+        bev = _events(torch, max(1, args.steps))
+        for e in bev:
+            e[0].record(stream)
+            b.replay(stream=stream)
+            e[1].record(stream)
+        torch.cuda.synchronize()
+        return sorted(a.elapsed_time(z) for a, z in bev)[len(bev) // 2]
+
     for k in orders:
         for _ in range(max(3, args.warmup)):
             plan.beamform(rf[0], k, outs[0], stream=stream)
@@ -456,17 +476,13 @@ def bench_small(args, torch):
         b2b_ms = e0.elapsed_time(e1)
         # the same frames as one persistent launch, replayed from a graph
         bt.set([plan] * n_frames, [rf[i % n_res] for i in range(n_frames)], [k] * n_frames, outs)
-        bt.capture()
-        for _ in range(2):
-            bt.replay(stream=stream)
-        torch.cuda.synchronize()
-        bev = _events(torch, max(1, args.steps))
-        for b in bev:
-            b[0].record(stream)
-            bt.replay(stream=stream)
-            b[1].record(stream)
-        torch.cuda.synchronize()
-        batch_ms = sorted(a.elapsed_time(z) for a, z in bev)[len(bev) // 2]
+        batch_ms = time_replays(bt)
+        paired = {}
+        if btm is not None:
+            btm.set([mplan] * n_frames, [rf[i % n_res] for i in range(n_frames)], [k] * n_frames, outs)
+            m_ms = time_replays(btm)
+            paired = {"batched_mirror_pairs_us_per_frame": round(m_ms * 1e3 / n_frames, 3),
+                      "batched_mirror_pairs_gpixch_s": round(pixch * n_frames / (m_ms * 1e-3) / 1e9, 2)}
         wall.sort()
         res["per_order"][str(k)] = {
             "latency_wall_us_p50": round(wall[len(wall) // 2], 2),
@@ -475,9 +491,12 @@ def bench_small(args, torch):
             "back_to_back_us_per_frame": round(b2b_ms * 1e3 / n_frames, 3),
             "back_to_back_gpixch_s": round(pixch * n_frames / (b2b_ms * 1e-3) / 1e9, 2),
             "batched_us_per_frame": round(batch_ms * 1e3 / n_frames, 3),
-            "batched_gpixch_s": round(pixch * n_frames / (batch_ms * 1e-3) / 1e9, 2)}
+            "batched_gpixch_s": round(pixch * n_frames / (batch_ms * 1e-3) / 1e9, 2), **paired}
     bt.close()
     plan.close()
+    if btm is not None:
+        btm.close()
+        mplan.close()
     print(json.dumps(res))
 
 
