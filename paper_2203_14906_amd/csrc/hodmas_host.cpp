@@ -336,9 +336,10 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     // LDS: `chunk` windows of `max_window` floats; shrink the chunk until it fits.
     const int64_t block = int64_t(p->tiling.tile_x) * p->tiling.tile_z * p->tiling.split;
     // split-group combination: (sum, compensation) of up to MAX_ORDER power
-    // sums plus the two coherence-factor sums per pixel
+    // sums plus the two coherence-factor sums per pixel, for each of `rows`
+    // pixels per lane, plus one padding float (an odd stride across lanes)
     const int64_t reduce_bytes = int64_t(block / p->tiling.split) * (p->tiling.split - 1) *
-                                 (HODMAS_MAX_ORDER + 2) * 2 * 4 * rows;
+                                 ((HODMAS_MAX_ORDER + 2) * 2 * rows + 1) * 4;
     // 40 KB keeps four workgroups on a CU (160 KB); an explicit chunk may use 64 KB
     const int64_t cap = auto_chunk ? 40 * 1024 : 64 * 1024;
     if (int64_t(p->max_window) * 4 * rows > hodmas::kMaxLdsBytes) {
@@ -448,7 +449,7 @@ hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int
     // LDS: the staged windows, or the cross-group combination of the power sums
     const int64_t nt = hodmas::kOrderSums;
     const int64_t block = int64_t(plan->tiling.tile_x) * plan->tiling.tile_z * plan->tiling.split;
-    const int64_t reduce = block / plan->tiling.split * (plan->tiling.split - 1) * 2 * nt * 4;
+    const int64_t reduce = block / plan->tiling.split * (plan->tiling.split - 1) * (2 * nt + 1) * 4;
     const int64_t lds = std::max<int64_t>(int64_t(plan->tiling.chunk) * plan->max_window * 4, reduce);
     if (lds > 64 * 1024)
         return HODMAS_EUNSUPPORTED;

@@ -504,7 +504,9 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
 
     if (A.split > 1) {
         // fixed-order combination of the groups' partial sums through LDS
-        constexpr int W = 2 * M * NS;          // floats per pixel and group
+        // floats per pixel and group: (sum, compensation) pairs, padded to an
+        // odd stride so consecutive lanes fall in different LDS banks
+        constexpr int W = 2 * M * NS + 1;
         __syncthreads();
         float* red = lds;
         if (g > 0) {
@@ -862,8 +864,8 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
             for (int j = 0; j < NT; ++j) {
                 if (!sum_needed(j, KMAX))
                     continue;
-                red[((g - 1) * npix + pl) * 2 * NT + 2 * j] = s[j];
-                red[((g - 1) * npix + pl) * 2 * NT + 2 * j + 1] = c[j];
+                red[((g - 1) * npix + pl) * (2 * NT + 1) + 2 * j] = s[j];
+                red[((g - 1) * npix + pl) * (2 * NT + 1) + 2 * j + 1] = c[j];
             }
         }
         __syncthreads();
@@ -873,8 +875,8 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
                 for (int j = 0; j < NT; ++j) {
                     if (!sum_needed(j, KMAX))
                         continue;
-                    const float so = red[((gg - 1) * npix + pl) * 2 * NT + 2 * j];
-                    const float co = red[((gg - 1) * npix + pl) * 2 * NT + 2 * j + 1];
+                    const float so = red[((gg - 1) * npix + pl) * (2 * NT + 1) + 2 * j];
+                    const float co = red[((gg - 1) * npix + pl) * (2 * NT + 1) + 2 * j + 1];
                     if (COMP) {
                         kahan_add(s[j], c[j], so);
                         kahan_add(s[j], c[j], -co);
