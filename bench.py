@@ -666,14 +666,16 @@ def bench_batch(args, torch):
 
 def bench_serve(args, torch):
     """Poisson arrivals at each rate for --duration s; continuous batching of
-    FP16 frames vs a plain synchronous FP32 launch per request."""
+    FP16 frames (mirror pairs unless --no-mirror) vs a plain synchronous FP32
+    launch per request."""
     from paper_2203_14906_amd import serve
-    pool = serve.FramePool(torch, "cuda", seed=5000)
+    pool = serve.FramePool(torch, "cuda", seed=5000, mirror=not args.no_mirror)
     out = {"metric": "p50/p99 latency and sustained frames/s, continuous batching vs plain FP32",
            "unit": "frames/s", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "Poisson arrivals, mixed N/S/grid/order frames from a pool of %d "
                                   "resident frames (%d resident plans)" % (len(pool.frames), len(pool._plans)),
-                      "duration_s": args.duration, "budget_gb": args.budget_gb},
+                      "duration_s": args.duration, "budget_gb": args.budget_gb,
+                      "fp16_mirror_pairs": not args.no_mirror},
            "rates": {}}
     warm = serve.poisson_requests(500.0, 0.5, len(pool.frames), seed=1)
     srv = serve.Server(torch, pool, slots=3, budget_bytes=int(args.budget_gb * (1 << 30)))

@@ -307,7 +307,9 @@ typedef struct {
 
 hodmas_status hodmas_batch_get_info(hodmas_batch_t batch, hodmas_batch_info* info);
 
-/* Release the batch (its graph and work-list buffers).  NULL is accepted. */
+/* Release the batch (its graph and work-list buffers).  Waits on the host for
+ * the batch's last launch, replay and work-list copy to finish first, so the
+ * buffers are never freed under a running kernel.  NULL is accepted. */
 hodmas_status hodmas_batch_destroy(hodmas_batch_t batch);
 
 /* Version string of the library. */

@@ -56,6 +56,7 @@ struct hodmas_batch_s {
     bool node_on[hodmas::kBatchKinds] = {};          // enabled in `exec`
     hipEvent_t replayed = nullptr;   // the last replay's completion
     bool replay_pending = false;
+    hipEvent_t launched = nullptr;   // the last direct launch's completion (destroy waits for it)
     hodmas_batch_info info{};
 };
 
@@ -63,6 +64,11 @@ namespace {
 
 void release(hodmas_batch_s* b)
 {
+    if (b->launched) {
+        (void)hipEventSynchronize(b->launched);
+        (void)hipEventDestroy(b->launched);
+        b->launched = nullptr;
+    }
     if (b->replayed) {
         (void)hipEventSynchronize(b->replayed);
         (void)hipEventDestroy(b->replayed);
@@ -137,7 +143,8 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
     b->bytes = b->off_units + align_up(sizeof(BatchUnit) * (size_t)max_units);
     if (hipMalloc((void**)&b->d_buf, b->bytes) != hipSuccess ||
         hipHostMalloc((void**)&b->h_buf, b->bytes, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->launched, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         release(b);
         delete b;
@@ -292,6 +299,10 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
             (void)hipGetLastError();
             return HODMAS_EDEVICE;
         }
+    }
+    if (hipEventRecord(b->launched, static_cast<hipStream_t>(stream)) != hipSuccess) {
+        (void)hipGetLastError();
+        return HODMAS_EDEVICE;
     }
     return HODMAS_OK;
 }

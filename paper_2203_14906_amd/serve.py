@@ -85,10 +85,12 @@ class FramePool:
 
     Shapes follow the mixed workload: N in {64,128,256}, S in {1024,2048,4096},
     square grids of side {256,512,768,1024}; ``per_shape`` distinct phantoms
-    per (N, S) are shared by the grid sides."""
+    per (N, S) are shared by the grid sides.  With ``mirror`` the FP16 plans
+    pair mirror tiles wherever the tiling allows it (the arrays are centred
+    and the grids symmetric about x = 0); the FP32 plans stay unpaired."""
 
     def __init__(self, torch, device, n_elements=(64, 128, 256), n_samples=(1024, 2048, 4096),
-                 sides=(256, 512, 768, 1024), per_shape=1, seed=5000, plain=True):
+                 sides=(256, 512, 768, 1024), per_shape=1, seed=5000, plain=True, mirror=False):
         self.torch = torch
         self.frames: list[PoolFrame] = []
         self._plans = {}
@@ -109,7 +111,14 @@ class FramePool:
                 w, d = ph.field_of_view(fr.n_elements, fr.n_samples)
                 grid = ph.make_grid(fr.side, fr.side, w, d)
                 geom = ph.Geometry(fr.n_elements)
-                p16 = hodmas.Plan(geom, grid, fr.n_samples, "f16", max_order=6)
+                p16 = None
+                if mirror:
+                    try:
+                        p16 = hodmas.Plan(geom, grid, fr.n_samples, "f16", max_order=6, flags=hodmas.FLAG_MIRROR)
+                    except hodmas.HodmasError:
+                        p16 = None   # no even split of the grid's tile columns: unpaired
+                if p16 is None:
+                    p16 = hodmas.Plan(geom, grid, fr.n_samples, "f16", max_order=6)
                 p32 = hodmas.Plan(geom, grid, fr.n_samples, "f32", max_order=6) if plain else None
                 self._plans[key] = (p16, p32)
             fr.plan16, fr.plan32 = self._plans[key]

@@ -96,3 +96,38 @@ def test_rejected_requests_leave_the_rest_intact(pool):
         fr = pool.frames[r.frame]
         assert r.status == "done" and torch.equal(fr.plan16.beamform(fr.rf16, r.order), r.image)
     srv.close()
+
+
+def test_server_with_mirror_pairs():
+    """The serving pool with paired FP16 plans: batches mix pair kinds of
+    several orders, and every request's image is still bitwise its frame's own
+    paired launch; a few are checked against the oracle (sign-change pixels
+    measured from the oracle's delay band)."""
+    from paper_2203_14906_amd import hodmas, serve
+    from sign_band import band_rel_l2
+    p = serve.FramePool(torch, "cuda", n_elements=(16, 32), n_samples=(256, 512), sides=(32, 48),
+                        seed=78, plain=False, mirror=True)
+    assert all(fr.plan16.info().flags & hodmas.FLAG_MIRROR for fr in p.frames)
+    reqs = serve.poisson_requests(4000.0, 0.06, len(p.frames), seed=6)
+    for r in reqs[:24]:
+        r.arrival = reqs[0].arrival
+    srv = serve.Server(torch, p, slots=3, budget_bytes=32 << 30, max_batch=8)
+    st = srv.run(reqs, keep_images=True)
+    torch.cuda.synchronize()
+    say("batched, mirror pairs:", st.summary())
+    assert all(r.status == "done" for r in reqs)
+    for r in reqs:
+        fr = p.frames[r.frame]
+        alone = fr.plan16.beamform(fr.rf16, r.order)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, r.image), "request %d differs from its alone result" % r.rid
+    for r in reqs[:6]:
+        fr = p.frames[r.frame]
+        w, d = ph.field_of_view(fr.n_elements, fr.n_samples)
+        grid = ph.make_grid(fr.side, fr.side, w, d)
+        err, flagged = band_rel_l2(r.image.cpu().numpy(), fr.rf16.cpu().numpy(), ph.Geometry(fr.n_elements),
+                                   grid, r.order)
+        say("request %d order %d rel L2 from the band %.2e (%d sign-change pixels)" % (r.rid, r.order, err, flagged))
+        assert err <= 2e-5
+    srv.close()
+    p.close()
