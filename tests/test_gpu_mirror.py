@@ -243,3 +243,25 @@ def test_mirror_batch_config2_matches_oracle_samples(hd):
         assert err <= 1e-5
     bt.close()
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["i16", "f16"])
+def test_mirror_config3_reduced_storage(hd, dtype):
+    """Config 3 at full size (256 elements, 2048 samples, 1024x1024) with
+    mirror pairs, as the reduced-precision bench times it: sampled pixels of
+    both halves against the oracle fed the same stored values."""
+    f = ph.config_frame(3)
+    arr, scale = stored(f.rf, dtype, seed=3000)
+    plan = hd.Plan(f.geometry, f.grid, arr.shape[1], dtype, max_order=6, dequant_scale=scale, flags=hd.FLAG_MIRROR)
+    dev = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    rng = np.random.default_rng(11)
+    ix = np.concatenate([rng.integers(0, f.grid.nx, 1500), [0, f.grid.nx - 1, f.grid.nx // 2 - 1, f.grid.nx // 2]])
+    iz = np.concatenate([rng.integers(0, f.grid.nz, 1500), [0, f.grid.nz - 1, 0, f.grid.nz - 1]])
+    for k in (1, 3, 6):
+        g = plan.beamform(dev, k).cpu().numpy().astype(np.float64)[iz, ix]
+        o = O.beamform(arr, f.geometry, f.grid, k, dequant_scale=scale if dtype == "i16" else None,
+                       pixels=(ix, iz))
+        err = rel_l2(g, o)
+        say("config 3 mirror %s k=%d sampled rel L2 %.2e" % (dtype, k, err))
+        assert err <= TOL[dtype]
+    plan.close()
