@@ -41,6 +41,9 @@ struct hodmas_batch_s {
     // persistent grid that LDS allows
     int64_t kind_lds[hodmas::kBatchKinds] = {};
     int kind_grid[hodmas::kBatchKinds] = {};
+    // the last occupancy answer per kind (a serving loop sets a list per launch)
+    int64_t occ_lds[hodmas::kBatchKinds] = {};
+    int occ_per_cu[hodmas::kBatchKinds] = {};
     size_t off_frames = 0, off_units = 0, bytes = 0;
     char* d_buf = nullptr;
     char* h_buf = nullptr;           // pinned staging of the work list
@@ -221,15 +224,19 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
     for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
         if (kl[kind] == 0)
             continue;
-        const void* fn = hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
-                                              hodmas::kind_pairing(kind), comp);
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)kl[kind]) !=
-                hipSuccess || per_cu < 1) {
-            (void)hipGetLastError();
-            return HODMAS_EDEVICE;
+        if (b->occ_lds[kind] != kl[kind]) {
+            const void* fn = hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
+                                                  hodmas::kind_pairing(kind), comp);
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)kl[kind]) !=
+                    hipSuccess || per_cu < 1) {
+                (void)hipGetLastError();
+                return HODMAS_EDEVICE;
+            }
+            b->occ_lds[kind] = kl[kind];
+            b->occ_per_cu[kind] = per_cu;
         }
-        kg[kind] = per_cu * b->cus;
+        kg[kind] = b->occ_per_cu[kind] * b->cus;
     }
     // grouped by kind (one persistent kernel each), heaviest units first within a kind
     std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) {
