@@ -261,8 +261,8 @@ typedef struct hodmas_batch_s* hodmas_batch_t;
  * on the current HIP device.  max_lds_bytes bounds the LDS any member
  * plan may need (0: the largest a workgroup can have).  Each kind of a work
  * list runs with the LDS of its own largest plan and as many persistent
- * workgroups as that LDS leaves room for.  flags: HODMAS_FLAG_ACC_PLAIN or 0; member plans must match it.
- * Errors: EINVAL, ENOMEM, EDEVICE. */
+ * workgroups as that LDS leaves room for.  flags: HODMAS_FLAG_ACC_PLAIN or 0;
+ * member plans must match it.  Errors: EINVAL, ENOMEM, EDEVICE. */
 hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t max_lds_bytes,
                                   uint32_t flags, hodmas_batch_t* out);
 
@@ -287,12 +287,13 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
 /* Build (once) a HIP graph holding the persistent kernels of every kind, with
  * no order between them (kinds write disjoint images, so one kind's tail
  * overlaps the next kind's start); they read the work list from device
- * memory, so later hodmas_batch_set calls need no re-capture.  hodmas_batch_replay launches that graph on `stream`, after
- * fitting the instantiated graph to the current work list: kinds absent from
- * it are switched off and each present kind gets its own LDS size and
- * persistent grid, at most one workgroup per unit.  When that changes a node, the replay first waits for the previous
- * replay of the graph to finish (host-side); replays of an unchanged kind mix
- * do not wait. */
+ * memory, so later hodmas_batch_set calls need no re-capture.
+ * hodmas_batch_replay launches that graph on `stream`, after fitting the
+ * instantiated graph to the current work list: kinds absent from it are
+ * switched off and each present kind gets its own LDS size and persistent
+ * grid, at most one workgroup per unit.  When that changes a node, the replay
+ * first waits for the previous replay of the graph to finish (host-side);
+ * replays of an unchanged kind mix do not wait. */
 hodmas_status hodmas_batch_capture(hodmas_batch_t batch);
 hodmas_status hodmas_batch_replay(hodmas_batch_t batch, void* stream);
 
