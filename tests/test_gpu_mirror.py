@@ -265,3 +265,42 @@ def test_mirror_config3_reduced_storage(hd, dtype):
         say("config 3 mirror %s k=%d sampled rel L2 %.2e" % (dtype, k, err))
         assert err <= TOL[dtype]
     plan.close()
+
+
+def test_mirror_batch_at_config4_sizes(hd):
+    """Paired FP16 plans of config-4 shapes (up to 256 elements, 4096 samples,
+    1024x1024) and mixed orders in one batch, as the mixed-batch bench runs
+    them: every image bitwise its own paired launch, sampled pixels within the
+    reduced-storage bar of the oracle on the same stored values."""
+    shapes = [(256, 4096, 1024, 6), (64, 1024, 256, 1), (128, 2048, 768, 4), (256, 2048, 512, 3)]
+    plans, devs, outs, orders, meta = [], [], [], [], []
+    for i, (n, S, side, k) in enumerate(shapes):
+        f = ph.make_frame(n, S, 8, 8, n_points=50, n_lines=3, snr_db=10.0, seed=4100 + i)
+        w, d = ph.field_of_view(n, S)
+        grid = ph.make_grid(side, side, w, d)
+        arr = ph.to_fp16(f.rf)
+        plans.append(hd.Plan(ph.Geometry(n), grid, S, "f16", max_order=6, flags=hd.FLAG_MIRROR))
+        devs.append(torch.from_numpy(arr).cuda())
+        outs.append(torch.empty((side, side), dtype=torch.float32, device="cuda"))
+        orders.append(k)
+        meta.append((arr, ph.Geometry(n), grid))
+    own = [p.beamform(d, k).cpu().numpy() for p, d, k in zip(plans, devs, orders)]
+    bt = hd.Batch(max_frames=len(plans), max_units=sum(p.info().n_tiles for p in plans),
+                  max_lds_bytes=max(p.info().lds_bytes for p in plans))
+    bt.set(plans, devs, orders, outs)
+    bt.capture()
+    bt.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    for i, (o, ref) in enumerate(zip(outs, own)):
+        img = o.cpu().numpy()
+        assert np.array_equal(img, ref), "frame %d differs from its own launch" % i
+        arr, geom, grid = meta[i]
+        ix, iz = rng.integers(0, grid.nx, 600), rng.integers(0, grid.nz, 600)
+        want = O.beamform(arr, geom, grid, orders[i], pixels=(ix, iz))
+        err = rel_l2(img[iz, ix].astype(np.float64), want)
+        say("config-4 shape %s k=%d mirror batch sampled rel L2 %.2e" % (shapes[i][:3], orders[i], err))
+        assert err <= TOL["f16"]
+    bt.close()
+    for p in plans:
+        p.close()
