@@ -30,16 +30,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU slots per pixel-channel for order k: the delay (4 FP32 ops +
-# sqrt + reciprocal), interpolation (6), the signed root, k-2 products and k
-# power-sum adds; every transcendental (sqrt, rcp, log2, exp2) weighs 4 slots,
-# being quarter-rate against the FP32 FMA issue rate.
-SLOTS = {1: 19, 2: 25, 3: 32, 4: 32, 5: 36, 6: 38}
+# Algorithmic work per pixel-channel for order k, in FP32 issue slots: 12 for
+# the delay, the sample index and fraction, the record test and the
+# interpolation; 2k for the powers and the power-sum adds (k-2 products and k
+# adds; one add at k = 1); 4 per transcendental (quarter rate), of which the
+# delay takes one and the signed root one (k = 2) or two (k >= 3).  The
+# roofline's `achieved` is ALGO_SLOTS[k] x pixel-channels / kernel time.
+ALGO_SLOTS = {1: 18, 2: 24, 3: 30, 4: 32, 5: 34, 6: 36}
 # 157.3 TFLOP/s FP32 vector (published) = 78.6e12 FMA lane-slots/s
 # (256 CUs x 128 FP32 lanes/clock x 2.4 GHz).
 VALU_PEAK_TSLOT = 78.64
-# The same work split into plain FP32 operations and transcendentals (SLOTS =
-# NONTRANS + 4 TRANS): the ceiling against the device's measured issue rates
+# The same work as this library's kernels spell it out per pixel-channel (the
+# delay as 4 FP32 ops + sqrt + reciprocal; interpolation 6; the signed root;
+# k-2 products; k adds), transcendentals weighted 4: reported beside the
+# roofline, not used for it.
+METHOD_SLOTS = {1: 19, 2: 25, 3: 32, 4: 32, 5: 36, 6: 38}
+# METHOD_SLOTS split into plain FP32 operations and transcendentals (METHOD_SLOTS
+# = NONTRANS + 4 TRANS): the ceiling against the device's measured issue rates
 # is 1 / (NONTRANS / R_fp32 + TRANS / R_trans) pixel-channels per second.
 NONTRANS = {1: 11, 2: 13, 3: 16, 4: 16, 5: 20, 6: 22}
 TRANS = {1: 2, 2: 3, 3: 4, 4: 4, 5: 4, 6: 4}
@@ -47,6 +54,11 @@ TRANS = {1: 2, 2: 3, 3: 4, 4: 4, 5: 4, 6: 4}
 # the roots of every order from shared transcendentals, and one add per
 # distinct power sum (1, 3, 5, 8, 12, 15 sums for orders up to 1..6).
 FUSED_SLOTS = {1: 19, 2: 26, 3: 38, 4: 47, 5: 59, 6: 68}
+
+
+def frac_of_peak(k, pixch, seconds):
+    """Fraction of the FP32 issue peak: ALGO_SLOTS[k] x pixel-channels / time."""
+    return ALGO_SLOTS[k] * pixch / seconds / 1e12 / VALU_PEAK_TSLOT
 
 
 def parse():
@@ -76,6 +88,12 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="batch: default tilings instead of the autotuner's")
     ap.add_argument("--tune-cache", default=os.path.join("/tmp", "hodmas_tune_cache.jsonl"),
                     help="batch and plain mirror pairs: autotuner cache file (JSON lines)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain: skip the short mixed-batch and serving runs embedded in its line")
+    ap.add_argument("--extra-rates", default="500,1000,2000,12000",
+                    help="plain: arrival rates of the embedded serving run (frames/s)")
+    ap.add_argument("--extra-duration", type=float, default=3.0,
+                    help="plain: seconds per rate of the embedded serving run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for HBM counter scaling)")
     return ap.parse_args()
@@ -109,6 +127,31 @@ def _profiled_traffic(kernel):
             line = line.strip()
             if line.startswith("traffic_bytes_per_launch " + kernel + ":"):
                 return int(line.rsplit(":", 1)[1])
+    return None
+
+
+def _issued_slots(kernel, pixch, seconds):
+    """The slots the kernel actually issues per pixel-channel -- plain VALU
+    instructions plus 4 per transcendental, from the committed rocprofv3
+    counter summary of the current kernel source -- and the fraction of the
+    peak they make at the measured time; None when no summary covers it.
+    Mirror pairs issue fewer slots than the algorithmic count (one delay
+    serves two pixels), so this fraction is the lower one for them."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2203_14906_amd", "csrc", "hodmas_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.md"))):
+        text = open(path).read()
+        if "kernel_source_sha256: " + sha not in text:
+            continue
+        for line in text.splitlines():
+            line = line.strip()
+            if line.startswith("issued_slots_per_pixch " + kernel + ":"):
+                slots = float(line.rsplit(":", 1)[1])
+                return {"slots_per_pixch": slots,
+                        "frac": round(slots * pixch / seconds / 1e12 / VALU_PEAK_TSLOT, 4),
+                        "source": os.path.basename(path)}
     return None
 
 
@@ -216,7 +259,7 @@ def bench_plain(args, torch):
     total_pixch = pixch * args.batch * len(orders) * args.steps
     value = total_pixch / elapsed / 1e9
     dom = max(orders, key=lambda k: per_order_ms[k])
-    achieved = SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
+    achieved = ALGO_SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
     dom_kernel = "%s<%d, f32, comp%s>" % ("hodmas_batch_kernel" if batched_step else "hodmas_frame_kernel", dom,
                                           ", mirror pairs" if mplan is not None else "")
 
@@ -254,6 +297,8 @@ def bench_plain(args, torch):
                 pf_ms = alt_ms
             others[key] = {"form": desc,
                            "kernel_us_per_frame": {str(k): round(v * 1e3, 3) for k, v in alt_ms.items()},
+                           "frac_of_peak": {str(k): round(frac_of_peak(k, pixch, v * 1e-3), 4)
+                                            for k, v in alt_ms.items()},
                            "gpixch_s_sum_orders": round(pixch * len(orders) / (sum(alt_ms.values()) * 1e-3) / 1e9,
                                                         2),
                            "headline_speedup": round(sum(alt_ms.values()) / sum(per_order_ms.values()), 3)}
@@ -336,27 +381,7 @@ def bench_plain(args, torch):
     # here only the CPU oracle's throughput on the same batch is measured.
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import oracle
-        # whole frames (every order) of the same batch, cycling, until at least
-        # 10 s of oracle work have run (never past ~30 s)
-        t_cpu = time.perf_counter()
-        n_pix = 0
-        n_frames = 0
-        while True:
-            b = n_frames % len(frames)
-            for k in orders:
-                oracle.beamform(rf_host[b], geom, grid, k)
-                n_pix += pixch
-            n_frames += 1
-            el = time.perf_counter() - t_cpu
-            if el >= 10.0 or el * (n_frames + 1) / n_frames > 30.0:
-                break
-        dt = time.perf_counter() - t_cpu
-        cpu = {"value": round(n_pix / dt / 1e9, 4), "unit": "Gpixel*ch/s", "cores": oracle.max_threads(),
-               "kind": "oracle",
-               "sample": "%d frame(s) (cycling over the %d of the batch) x orders %s, FP64, %.1f s" %
-                         (n_frames, len(frames), ",".join(map(str, orders)), dt)}
-
+        cpu = _cpu_baseline(rf_host, geom, grid, orders, pixch)
     res = {
         "metric": "beamformed Gpixel*ch/s (sum over orders k=%s)" % ",".join(map(str, orders)),
         "value": round(value, 2),
@@ -386,20 +411,73 @@ def bench_plain(args, torch):
         "roofline": {"bound": "alu", "kernel": dom_kernel,
                      "achieved": round(achieved, 2), "peak": VALU_PEAK_TSLOT, "unit": "Tslot/s",
                      "frac": round(achieved / VALU_PEAK_TSLOT, 4),
-                     "slots_per_pixch": SLOTS[dom],
-                     "slots_model": "the method's slots per pixel-channel (one delay per pixel and element); "
-                                    "mirror pairs share each delay between two pixels, so their kernels "
-                                    "issue fewer" if mplan is not None else "the method's slots per pixel-channel",
+                     "slots_per_pixch": ALGO_SLOTS[dom],
+                     "slots_model": "algorithmic FP32 issue slots per pixel-channel: 12 + 2k + 4 per "
+                                    "transcendental (18/24/30/32/34/36 for k=1..6)",
+                     "frac_method_slots": round(METHOD_SLOTS[dom] * pixch / (per_order_ms[dom] * 1e-3) / 1e12
+                                                / VALU_PEAK_TSLOT, 4),
+                     "issued": _issued_slots(dom_kernel, pixch, per_order_ms[dom] * 1e-3),
                      "traffic": _profiled_traffic(dom_kernel),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "measured": measured},
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_extras:
+        # the metric's second half: frames/s and latency, batched vs plain, on
+        # the mixed 256-frame batch and under Poisson arrivals (short runs)
+        res["config4_batched_vs_plain"] = batch_workload(args, torch)
+        res["config5_serving"] = serve_workload(args, torch, [float(r) for r in args.extra_rates.split(",")],
+                                                args.extra_duration)
     print(json.dumps(res))
     plan.close()
     if mplan is not None:
         mplan.close()
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _cpu_baseline(rf_host, geom, grid, orders, pixch):
+    """The FP64 oracle on this host's cores: whole frames of the batch at every
+    order, cycling, for at least 8 s on all threads (never past ~25 s), then
+    one frame's orders on one thread (at least 3 s)."""
+    from oracle import oracle
+
+    def timed(min_s, max_s):
+        t0 = time.perf_counter()
+        n_pix = n_frames = 0
+        while True:
+            b = n_frames % len(rf_host)
+            for k in orders:
+                oracle.beamform(rf_host[b], geom, grid, k)
+                n_pix += pixch
+            n_frames += 1
+            el = time.perf_counter() - t0
+            if el >= min_s or el * (n_frames + 1) / n_frames > max_s:
+                return n_pix, n_frames, time.perf_counter() - t0
+
+    threads = oracle.max_threads()
+    n_pix, n_frames, dt = timed(8.0, 25.0)
+    oracle.set_threads(1)
+    try:
+        n1, f1, dt1 = timed(3.0, 12.0)
+    finally:
+        oracle.set_threads(threads)
+    return {"value": round(n_pix / dt / 1e9, 4), "unit": "Gpixel*ch/s", "cores": threads, "kind": "oracle",
+            "sample": "%d frame(s) (cycling over the %d of the batch) x orders %s, FP64, %.1f s"
+                      % (n_frames, len(rf_host), ",".join(map(str, orders)), dt),
+            "one_thread": {"value": round(n1 / dt1 / 1e9, 4), "cores": 1,
+                           "sample": "%d frame(s) x orders %s, %.1f s" % (f1, ",".join(map(str, orders)), dt1)},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def bench_small(args, torch):
@@ -588,6 +666,10 @@ def _mixed_frames(torch, specs, with_fp32, tune_cache=None, mirror=False):
 
 
 def bench_batch(args, torch):
+    print(json.dumps(batch_workload(args, torch)))
+
+
+def batch_workload(args, torch):
     """256 mixed frames (N, S, grid side, order drawn per frame; FP16 RF) in one
     persistent launch replayed from a HIP graph, with mirror pairs (--no-mirror:
     unpaired), against 256 plain per-frame FP32 launches on one stream.  All frames are submitted at t = 0; latency is
@@ -657,15 +739,19 @@ def bench_batch(args, torch):
            "speedup": round(tp_ms / tb_ms, 3),
            "rel_l2_batched_fp16_vs_plain_fp32_first16": float("%.3e" % worst),
            "pixel_channels": pixch}
-    print(json.dumps(res))
     batch.close()
     for p16, p32 in plans.values():
         p16.close()
         p32.close()
+    return res
 
 
 def bench_serve(args, torch):
-    """Poisson arrivals at each rate for --duration s; continuous batching of
+    print(json.dumps(serve_workload(args, torch, [float(r) for r in args.rates.split(",")], args.duration)))
+
+
+def serve_workload(args, torch, rates, duration):
+    """Poisson arrivals at each rate for `duration` s; continuous batching of
     FP16 frames (mirror pairs unless --no-mirror) vs a plain synchronous FP32
     launch per request."""
     from paper_2203_14906_amd import serve
@@ -674,23 +760,23 @@ def bench_serve(args, torch):
            "unit": "frames/s", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "Poisson arrivals, mixed N/S/grid/order frames from a pool of %d "
                                   "resident frames (%d resident plans)" % (len(pool.frames), len(pool._plans)),
-                      "duration_s": args.duration, "budget_gb": args.budget_gb,
+                      "duration_s": duration, "budget_gb": args.budget_gb,
                       "fp16_mirror_pairs": not args.no_mirror},
            "rates": {}}
     warm = serve.poisson_requests(500.0, 0.5, len(pool.frames), seed=1)
     srv = serve.Server(torch, pool, slots=3, budget_bytes=int(args.budget_gb * (1 << 30)))
     srv.run(warm)
     serve.run_plain(torch, pool, warm[:50])
-    for rate in [float(r) for r in args.rates.split(",")]:
-        reqs = serve.poisson_requests(rate, args.duration, len(pool.frames), seed=int(rate))
+    for rate in rates:
+        reqs = serve.poisson_requests(rate, duration, len(pool.frames), seed=int(rate))
         b = srv.run(reqs).summary()
-        reqs = serve.poisson_requests(rate, args.duration, len(pool.frames), seed=int(rate))
+        reqs = serve.poisson_requests(rate, duration, len(pool.frames), seed=int(rate))
         p = serve.run_plain(torch, pool, reqs).summary()
         out["rates"][str(int(rate))] = {"batched": b, "plain_fp32": p}
         print("rate %g: batched %s | plain %s" % (rate, b, p), file=sys.stderr, flush=True)
     srv.close()
     pool.close()
-    print(json.dumps(out))
+    return out
 
 
 

@@ -41,7 +41,8 @@
 
 /* Time of flight in samples from pixel (xp, zp) to an element at (xe, 0).
  * One-way propagation (the pixel is the source), time origin at the laser
- * shot shifted by t0 (Sec. II-A: "time delay of that element"). */
+ * shot shifted by t0 (Sec. II-A, Eq. 1: the per-element delay applied to
+ * each channel before summation). */
 double hodmas_oracle_tof(double xe, double xp, double zp, double c, double fs, double t0)
 {
     double dx = xp - xe;
@@ -224,5 +225,17 @@ int hodmas_oracle_max_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads later parallel regions of this library use (n >= 1); timing only,
+ * the results do not depend on it. */
+void hodmas_oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

@@ -58,6 +58,8 @@ def lib():
                                                     d, d, d, d, i32, i64, pi32, pi32, pd]
         L.hodmas_oracle_max_threads.restype = i32
         L.hodmas_oracle_max_threads.argtypes = []
+        L.hodmas_oracle_set_threads.restype = None
+        L.hodmas_oracle_set_threads.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -147,3 +149,8 @@ def beamform(rf, geometry, grid, order, dequant_scale=None, pixels=None, weighti
 
 def max_threads() -> int:
     return int(lib().hodmas_oracle_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (timing only; results do not depend on it)."""
+    lib().hodmas_oracle_set_threads(int(n))

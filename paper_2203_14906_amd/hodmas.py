@@ -346,8 +346,9 @@ class Batch:
             raise ValueError("plans, rfs, orders and images must have the same length")
         for p, r, o in zip(plans, rfs, images):
             _check_tensor(r, p)
-            if o.dtype.__str__() != "torch.float32" or not o.is_contiguous() or o.numel() != p.nx * p.nz:
-                raise ValueError("each image must be a contiguous float32 tensor of nz*nx elements")
+            if not o.is_cuda or o.dtype.__str__() != "torch.float32" or not o.is_contiguous() or \
+                    o.numel() != p.nx * p.nz:
+                raise ValueError("each image must be a contiguous float32 GPU tensor of nz*nx elements")
         ph = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
         pr = (ctypes.c_void_p * n)(*[r.data_ptr() for r in rfs])
         po = (ctypes.c_int32 * n)(*[int(k) for k in orders])

@@ -55,10 +55,21 @@ class ServeStats:
     rejected: int = 0            # refused on arrival (unknown frame, order outside 1..6)
     dropped: int = 0             # deadline passed before launch
     failed: int = 0              # the library refused the launch of this request
+    batch_sizes: list = field(default_factory=list)   # requests per launch, in launch order
+
+    def launch_histogram(self) -> dict:
+        """Launches by the number of requests they carried (1, 2-3, 4-7, ...)."""
+        hist = {}
+        for n in self.batch_sizes:
+            lo = 1 << (int(n).bit_length() - 1)
+            key = "1" if lo == 1 else "%d-%d" % (lo, 2 * lo - 1)
+            hist[key] = hist.get(key, 0) + 1
+        return dict(sorted(hist.items(), key=lambda kv: int(kv[0].split("-")[0])))
 
     def summary(self) -> dict:
         lat = self.latencies_ms
         served = self.n_requests - self.rejected - self.dropped - self.failed
+        sizes = np.asarray(self.batch_sizes, dtype=np.float64)
         return {"mode": self.mode, "requests": self.n_requests,
                 "frames_per_s": round(served / self.wall_s, 2) if self.wall_s > 0 else None,
                 "p50_ms": round(float(np.percentile(lat, 50)), 3) if lat.size else None,
@@ -66,7 +77,10 @@ class ServeStats:
                 "mean_ms": round(float(lat.mean()), 3) if lat.size else None,
                 "launches": self.launches, "max_inflight_requests": self.max_inflight,
                 "admission_waits": self.admission_waits, "rejected": self.rejected,
-                "dropped": self.dropped, "failed": self.failed}
+                "dropped": self.dropped, "failed": self.failed,
+                "requests_per_launch": {"mean": round(float(sizes.mean()), 2) if sizes.size else None,
+                                        "max": int(sizes.max()) if sizes.size else None,
+                                        "histogram": self.launch_histogram()}}
 
 
 @dataclass
@@ -318,6 +332,7 @@ class Server:
                     inflight[i] = (handle, take)
                     state["reqs"] += len(take)
                     stats.launches += 1
+                    stats.batch_sizes.append(len(take))
                     stats.max_inflight = max(stats.max_inflight, state["reqs"])
                     break
             if state["finished"] < total:
@@ -351,6 +366,7 @@ def run_plain(torch, pool: FramePool, requests: list[Request], keep_images=False
         r.done = time.perf_counter() - t0
         r.status = "done"
         stats.launches += 1
+        stats.batch_sizes.append(1)
         if not keep_images:
             r.image = None
     stats.wall_s = max(r.done for r in requests) if requests else 0.0

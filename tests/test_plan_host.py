@@ -326,3 +326,48 @@ def test_mirror_pixels_read_the_mirrored_delays(n_elem, tiling):
     assert n_checked > 0                                           # tiles at the record's end
     assert n_skipped > 0 or n_elem == 24                           # elements left out of tiles
     plan.close()
+
+
+class _DeviceTensorStub:
+    """Stands for a GPU tensor in the binding's argument checks (no device here)."""
+
+    def __init__(self, shape, dtype, is_cuda=True):
+        import torch
+        self.shape = shape
+        self.dtype = dtype
+        self.is_cuda = is_cuda
+        self._t = torch.empty(shape, dtype=dtype)
+
+    def dim(self):
+        return len(self.shape)
+
+    def stride(self, i):
+        return self._t.stride(i)
+
+    def is_contiguous(self):
+        return True
+
+    def numel(self):
+        return self._t.numel()
+
+    def data_ptr(self):
+        raise AssertionError("the binding passed a pointer before rejecting the arguments")
+
+
+def test_batch_set_rejects_host_images_before_any_launch():
+    """A host (CPU) image would hand the persistent kernel a host address; the
+    binding refuses it before any library call."""
+    import torch
+    f = ph.make_frame(8, 128, 16, 16, n_points=2, n_lines=0, snr_db=20.0, seed=1)
+    plan = _plan(f.geometry, f.grid, 128)
+    bt = hodmas.Batch.__new__(hodmas.Batch)          # no device: the library handle is never used
+    bt._h = ctypes.c_void_p()
+    bt._keep = None
+    rf = _DeviceTensorStub((8, 128), torch.float32)
+    host_img = torch.empty((16, 16), dtype=torch.float32)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        bt.set([plan], [rf], [1], [host_img])
+    wrong = _DeviceTensorStub((16, 16), torch.float64)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        bt.set([plan], [rf], [1], [wrong])
+    plan.close()

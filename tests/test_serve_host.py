@@ -127,3 +127,16 @@ def test_a_refused_request_fails_alone():
     # the refused batch was relaunched one request at a time
     assert all(len(rids) == 1 for _, rids, _ in ex.launched)
     assert sorted(rid for _, rids, _ in ex.launched for rid in rids) == [0, 1, 2, 4, 5]
+
+
+def test_requests_per_launch_are_reported():
+    clock, pool = FakeClock(), _pool()
+    ex = FakeExecutor(clock, n_slots=1, latency=5e-3)
+    # one slot, max_batch 3: a burst of 8 goes out as 3 + 3 + 2
+    st = _server(pool, ex, clock, max_batch=3).run(_burst(8))
+    assert st.batch_sizes == [len(rids) for _, rids, _ in ex.launched] == [3, 3, 2]
+    s = st.summary()["requests_per_launch"]
+    assert s["max"] == 3 and abs(s["mean"] - 8 / 3) < 0.01
+    assert s["histogram"] == {"2-3": 3}
+    assert serve.ServeStats("x", 0, 0.0, batch_sizes=[1, 1, 4, 9, 17, 40]).launch_histogram() == \
+        {"1": 2, "4-7": 1, "8-15": 1, "16-31": 1, "32-63": 1}
