@@ -362,6 +362,27 @@ hodmas_status hodmas_display_run(hodmas_display_t display, const float* image_de
 /* Release a display plan.  NULL is accepted. */
 hodmas_status hodmas_display_destroy(hodmas_display_t display);
 
+/* The display chain of hodmas_display_run without a plan and without any
+ * allocation, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * calls no hipMalloc, hipFree or other allocating routine.  The band-pass
+ * taps, FFT twiddles and per-workgroup envelope maxima live in a file-scope
+ * device array of 289 KiB (256 taps, 4096 twiddles, 65536 maxima) that each
+ * GPU holds until the process ends; its device address is looked up once per
+ * device, on the first call there.  Three asynchronous launches on `stream`:
+ * the tables, the envelope, the dB image -- the same arithmetic as the plan
+ * path.  desc, image_dev, envelope_dev and db_dev as for hodmas_display_plan
+ * and hodmas_display_run (caller-owned device buffers, [nz][nx] float32).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe.
+ * Errors: EINVAL (as for hodmas_display_plan and hodmas_display_run),
+ * EUNSUPPORTED (nx above 65536, more workgroup maxima than the array holds),
+ * EDEVICE (no current device, the array's address unavailable, a failed
+ * launch). */
+hodmas_status hodmas_display_run_static(const hodmas_display_desc* desc, const float* image_dev,
+                                        float* envelope_dev, float* db_dev, void* stream);
+
 /* -------------------------------------------------------------------------
  * Image-quality metrics (Sec. IV): SNR = 20 log10(mu_in / sigma_out)
  * (Eq. 10), CR = 20 log10(mu_in / mu_out) (Eq. 11) and

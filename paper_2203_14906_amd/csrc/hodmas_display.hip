@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -179,6 +180,49 @@ __global__ __launch_bounds__(kDispBlock) void log_compress_kernel(const float* _
     }
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free form (hodmas_display_run_static).  Its band-pass taps, FFT
+// twiddles and per-workgroup envelope maxima live in this file-scope device
+// array instead of buffers a plan allocates.  Every GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for that device.
+constexpr int kStaticTapFloats = 256;                   // taps (numtaps <= 255)
+constexpr int kStaticTwiddles = kMaxNz / 2;             // float2 twiddles
+constexpr int kStaticMaxBlocks = 65536;                 // one maximum per workgroup (nx <= 65536)
+constexpr size_t kStaticTwiddleOffset = sizeof(float) * kStaticTapFloats;
+constexpr size_t kStaticBlockMaxOffset = kStaticTwiddleOffset + sizeof(float2) * kStaticTwiddles;
+constexpr size_t kStaticScratchBytes = kStaticBlockMaxOffset + sizeof(float) * kStaticMaxBlocks;
+static_assert(kStaticTwiddleOffset % 8 == 0 && kStaticBlockMaxOffset % 4 == 0, "scratch regions aligned");
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Columns per envelope workgroup: as many as the LDS budget allows, but few
+// enough that the grid still gives every CU two workgroups.
+int display_cols(int nx, int nz, int cus)
+{
+    return std::max(1, std::min({16, kDispColsBudget / nz, nx / (2 * cus)}));
+}
+
+struct StaticTaps {
+    float v[kMaxTaps];
+};
+
+// The taps (from the kernel arguments) and the twiddles exp(-2 pi i t / nz),
+// t < nz / 2, evaluated in float64 and rounded to float as the plan does.
+__global__ __launch_bounds__(kDispBlock) void static_tables_kernel(StaticTaps taps, int numtaps, int nz,
+                                                                   float* __restrict__ d_taps,
+                                                                   float2* __restrict__ d_tw)
+{
+    const int i = blockIdx.x * kDispBlock + threadIdx.x;
+    if (i < numtaps)
+        d_taps[i] = taps.v[i];
+    if (i < nz / 2) {
+        double sn, cs;
+        sincospi(-2.0 * double(i) / double(nz), &sn, &cs);
+        d_tw[i] = make_float2((float)cs, (float)sn);
+    }
+}
+
 }  // namespace
 
 struct hodmas_display_s {
@@ -239,8 +283,6 @@ hodmas_status hodmas_display_plan(const hodmas_display_desc* d, hodmas_display_t
     p->desc = *d;
     while ((1 << p->log2n) < d->nz)
         ++p->log2n;
-    // columns per workgroup: as many as the LDS budget allows, but few enough
-    // that the grid still gives every CU two workgroups
     int cus = 256;
     {
         int dev = 0;
@@ -248,7 +290,7 @@ hodmas_status hodmas_display_plan(const hodmas_display_desc* d, hodmas_display_t
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
             cus = prop.multiProcessorCount;
     }
-    p->cols = std::max(1, std::min({16, kDispColsBudget / d->nz, d->nx / (2 * cus)}));
+    p->cols = display_cols(d->nx, d->nz, cus);
     p->n_blocks = (d->nx + p->cols - 1) / p->cols;
     std::vector<float> ft(d->numtaps);
     for (int k = 0; k < d->numtaps; ++k)
@@ -304,6 +346,112 @@ hodmas_status hodmas_display_run(hodmas_display_t p, const float* image_dev, flo
     }
     if (cur != p->device)
         (void)hipSetDevice(cur);
+    return e == hipSuccess ? HODMAS_OK : HODMAS_EDEVICE;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticDevice {
+    bool ready = false;
+    void* scratch = nullptr;      // device address of `scratch` on this device
+    int cus = 256;
+};
+
+std::mutex g_static_mu;
+StaticDevice g_static[kMaxDevices];
+
+// First call on a device: the device address of its scratch array, its CU
+// count, and the LDS limit of the envelope kernel.  Returns null on failure.
+const StaticDevice* static_device(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticDevice& sd = g_static[dev];
+    if (!sd.ready) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        const int lds_max = (int)(sizeof(float) * 2 * (size_t)(kDispColsBudget + 16));
+        if (hipFuncSetAttribute((const void*)envelope_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                lds_max) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        sd.scratch = ptr;
+        sd.cus = prop.multiProcessorCount;
+        sd.ready = true;
+    }
+    return &sd;
+}
+
+}  // namespace
+
+extern "C" {
+
+hodmas_status hodmas_display_run_static(const hodmas_display_desc* d, const float* image_dev, float* envelope_dev,
+                                        float* db_dev, void* stream)
+{
+    if (!d || !image_dev || !db_dev || image_dev == db_dev || image_dev == envelope_dev)
+        return HODMAS_EINVAL;
+    if (d->nx < 1 || d->nz < 2 || d->nz > kMaxNz || (d->nz & (d->nz - 1)) != 0 || !(d->dynamic_range_db > 0.f))
+        return HODMAS_EINVAL;
+    if (d->nx > kStaticMaxBlocks)
+        return HODMAS_EUNSUPPORTED;             // more workgroup maxima than the scratch array holds
+    double taps[kMaxTaps];
+    const hodmas_status tst = hodmas_display_taps(d, taps);
+    if (tst != HODMAS_OK)
+        return tst;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return HODMAS_EDEVICE;
+    const StaticDevice* sd = static_device(dev);
+    if (!sd)
+        return HODMAS_EDEVICE;
+    int log2n = 0;
+    while ((1 << log2n) < d->nz)
+        ++log2n;
+    const int cols = display_cols(d->nx, d->nz, sd->cus);
+    const int n_blocks = (d->nx + cols - 1) / cols;
+    if (n_blocks > kStaticMaxBlocks)
+        return HODMAS_EUNSUPPORTED;
+    StaticTaps ft;
+    for (int k = 0; k < kMaxTaps; ++k)
+        ft.v[k] = k < d->numtaps ? (float)taps[k] : 0.f;
+    unsigned char* base = static_cast<unsigned char*>(sd->scratch);
+    float* d_taps = reinterpret_cast<float*>(base);
+    float2* d_tw = reinterpret_cast<float2*>(base + kStaticTwiddleOffset);
+    float* d_block_max = reinterpret_cast<float*>(base + kStaticBlockMaxOffset);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n_tab = std::max(d->numtaps, d->nz / 2);
+    hipLaunchKernelGGL(static_tables_kernel, dim3((n_tab + kDispBlock - 1) / kDispBlock), dim3(kDispBlock), 0, st,
+                       ft, d->numtaps, d->nz, d_taps, d_tw);
+    hipError_t e = hipGetLastError();
+    float* env = envelope_dev ? envelope_dev : db_dev;
+    if (e == hipSuccess) {
+        const size_t lds = sizeof(float) * 2 * (size_t)cols * (d->nz + 1);
+        hipLaunchKernelGGL(envelope_kernel, dim3(n_blocks), dim3(kDispBlock), lds, st, image_dev, env, d->nx,
+                           d->nz, log2n, cols, d_taps, d->numtaps, d_tw, d_block_max);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        const int64_t count = (int64_t)d->nx * d->nz;
+        const int grid = (int)std::min<int64_t>((count + kDispBlock - 1) / kDispBlock, 4096);
+        hipLaunchKernelGGL(log_compress_kernel, dim3(grid), dim3(kDispBlock), 0, st, env, db_dev, count,
+                           d_block_max, n_blocks, d->dynamic_range_db);
+        e = hipGetLastError();
+    }
     return e == hipSuccess ? HODMAS_OK : HODMAS_EDEVICE;
 }
 

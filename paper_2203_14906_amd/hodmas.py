@@ -171,6 +171,8 @@ def _load():
     L.hodmas_display_run.argtypes = [vp, vp, vp, vp, vp]
     L.hodmas_display_destroy.restype = i32
     L.hodmas_display_destroy.argtypes = [vp]
+    L.hodmas_display_run_static.restype = i32
+    L.hodmas_display_run_static.argtypes = [ctypes.POINTER(DisplayDesc), vp, vp, vp, vp]
     L.hodmas_image_metrics.restype = i32
     L.hodmas_image_metrics.argtypes = [vp, i32, i32, ctypes.c_double, ctypes.POINTER(Rect), ctypes.POINTER(Rect),
                                        i32, vp, ctypes.POINTER(Metrics)]
@@ -410,6 +412,27 @@ def display_taps(nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps, nx=1, dyn
     out = (ctypes.c_double * max(1, int(numtaps)))()
     _check(lib.hodmas_display_taps(ctypes.byref(d), out), "hodmas_display_taps")
     return [out[i] for i in range(int(numtaps))]
+
+
+def display_static(image, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps=63, dynamic_range_db=60.0,
+                   envelope=None, db=None, stream=None):
+    """hodmas_display_run_static: the display chain of one image without a
+    plan; its scratch is a fixed device array of the library.  The outputs
+    must be given (this call allocates nothing)."""
+    import torch
+    if db is None:
+        raise ValueError("db must be given: this call allocates nothing")
+    for t in (image, envelope, db):
+        if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                              or t.dim() != 2 or tuple(t.shape) != tuple(image.shape)):
+            raise ValueError("images must be contiguous float32 GPU tensors [nz][nx] of one shape")
+    nz, nx = image.shape
+    d = _display_desc(nx, nz, dz_m, sound_speed_m_s, f_lo_hz, f_hi_hz, numtaps, dynamic_range_db)
+    _check(lib.hodmas_display_run_static(ctypes.byref(d), ctypes.c_void_p(image.data_ptr()),
+                                         ctypes.c_void_p(envelope.data_ptr()) if envelope is not None else None,
+                                         ctypes.c_void_p(db.data_ptr()), _stream_handle(stream)),
+           "hodmas_display_run_static")
+    return envelope, db
 
 
 class Display:
