@@ -90,7 +90,7 @@ def parse():
                     help="batch and plain mirror pairs: autotuner cache file (JSON lines)")
     ap.add_argument("--no-extras", action="store_true",
                     help="plain: skip the short mixed-batch and serving runs embedded in its line")
-    ap.add_argument("--extra-rates", default="500,1000,2000,12000",
+    ap.add_argument("--extra-rates", default="500,2000,16000,24000",
                     help="plain: arrival rates of the embedded serving run (frames/s)")
     ap.add_argument("--extra-duration", type=float, default=3.0,
                     help="plain: seconds per rate of the embedded serving run")
@@ -486,7 +486,9 @@ def bench_small(args, torch):
     overhead: report single-launch latency (host wall clock of launch plus
     synchronize, and the kernel's own time from HIP events) and throughput over
     1024 back-to-back frames, as per-frame launches and as one persistent batch
-    launch replayed from a HIP graph (unpaired and with mirror pairs)."""
+    launch (unpaired and with mirror pairs; the batch plans take the tiling the
+    autotuner picks for batches, and the graph replay is timed beside the
+    direct launch)."""
     from paper_2203_14906_amd import hodmas, phantom as ph
     dev = torch.device("cuda:0")
     p = ph.CONFIGS[1]
@@ -494,8 +496,9 @@ def bench_small(args, torch):
     n_res, n_frames = 16, 1024                    # resident records, frames per throughput run
     frames = [ph.config_frame(1, b) for b in range(n_res)]
     geom, grid = frames[0].geometry, frames[0].grid
+    S = p["n_samples"]
     pixch = grid.nx * grid.nz * p["n_elements"]
-    plan = hodmas.Plan(geom, grid, p["n_samples"], "f32", max_order=max(orders))
+    plan = hodmas.Plan(geom, grid, S, "f32", max_order=max(orders))
     info = plan.info()
     rf = [torch.from_numpy(ph.to_fp32(fr.rf)).to(dev) for fr in frames]
     outs = [torch.empty((grid.nz, grid.nx), dtype=torch.float32, device=dev) for _ in range(n_frames)]
@@ -506,26 +509,30 @@ def bench_small(args, torch):
                       "tiling": [info.tiling.tile_x, info.tiling.tile_z, info.tiling.split, info.tiling.chunk],
                       "n_tiles": info.n_tiles, "frames_back_to_back": n_frames},
            "per_order": {}}
-    bt = hodmas.Batch(max_frames=n_frames, max_units=info.n_tiles * n_frames, max_lds_bytes=info.lds_bytes)
-    # the batched form again with mirror pairs (the array and grid are symmetric)
-    mplan = btm = None
-    if not args.no_mirror:
-        mplan = hodmas.Plan(geom, grid, p["n_samples"], "f32", max_order=max(orders), flags=hodmas.FLAG_MIRROR)
-        mi = mplan.info()
-        btm = hodmas.Batch(max_frames=n_frames, max_units=mi.n_tiles * n_frames, max_lds_bytes=mi.lds_bytes)
+    batch_rf = [rf[i % n_res] for i in range(n_frames)]
 
-    def time_replays(b):
-        b.capture()
-        for _ in range(2):
-            b.replay(stream=stream)
-        torch.cuda.synchronize()
-        bev = _events(torch, max(1, args.steps))
-        for e in bev:
-            e[0].record(stream)
-            b.replay(stream=stream)
-            e[1].record(stream)
-        torch.cuda.synchronize()
-        return sorted(a.elapsed_time(z) for a, z in bev)[len(bev) // 2]
+    def time_batch(q, k):
+        """(direct launch ms, graph replay ms) for the n_frames frames under plan q."""
+        qi = q.info()
+        b = hodmas.Batch(max_frames=n_frames, max_units=qi.n_tiles * n_frames, max_lds_bytes=qi.lds_bytes)
+        b.set([q] * n_frames, batch_rf, [k] * n_frames, outs)
+        out = []
+        for replay in (False, True):
+            if replay:
+                b.capture()
+            run = (lambda: b.replay(stream=stream)) if replay else (lambda: b.launch(stream=stream))
+            for _ in range(2):
+                run()
+            torch.cuda.synchronize()
+            bev = _events(torch, max(3, args.steps))
+            for e in bev:
+                e[0].record(stream)
+                run()
+                e[1].record(stream)
+            torch.cuda.synchronize()
+            out.append(sorted(a.elapsed_time(z) for a, z in bev)[len(bev) // 2])
+        b.close()
+        return out
 
     for k in orders:
         for _ in range(max(3, args.warmup)):
@@ -552,29 +559,30 @@ def bench_small(args, torch):
         e1.record(stream)
         torch.cuda.synchronize()
         b2b_ms = e0.elapsed_time(e1)
-        # the same frames as one persistent launch, replayed from a graph
-        bt.set([plan] * n_frames, [rf[i % n_res] for i in range(n_frames)], [k] * n_frames, outs)
-        batch_ms = time_replays(bt)
-        paired = {}
-        if btm is not None:
-            btm.set([mplan] * n_frames, [rf[i % n_res] for i in range(n_frames)], [k] * n_frames, outs)
-            m_ms = time_replays(btm)
-            paired = {"batched_mirror_pairs_us_per_frame": round(m_ms * 1e3 / n_frames, 3),
-                      "batched_mirror_pairs_gpixch_s": round(pixch * n_frames / (m_ms * 1e-3) / 1e9, 2)}
         wall.sort()
-        res["per_order"][str(k)] = {
-            "latency_wall_us_p50": round(wall[len(wall) // 2], 2),
-            "latency_wall_us_p99": round(wall[int(0.99 * (len(wall) - 1))], 2),
-            "kernel_us_p50": round(kern[len(kern) // 2], 2),
-            "back_to_back_us_per_frame": round(b2b_ms * 1e3 / n_frames, 3),
-            "back_to_back_gpixch_s": round(pixch * n_frames / (b2b_ms * 1e-3) / 1e9, 2),
-            "batched_us_per_frame": round(batch_ms * 1e3 / n_frames, 3),
-            "batched_gpixch_s": round(pixch * n_frames / (batch_ms * 1e-3) / 1e9, 2), **paired}
-    bt.close()
+        row = {"latency_wall_us_p50": round(wall[len(wall) // 2], 2),
+               "latency_wall_us_p99": round(wall[int(0.99 * (len(wall) - 1))], 2),
+               "kernel_us_p50": round(kern[len(kern) // 2], 2),
+               "back_to_back_us_per_frame": round(b2b_ms * 1e3 / n_frames, 3),
+               "back_to_back_gpixch_s": round(pixch * n_frames / (b2b_ms * 1e-3) / 1e9, 2)}
+        # the same frames as one persistent launch, with the tiling the
+        # autotuner picks for batches (timed as a batch runs them)
+        for name, flags in (("batched", 0), ("batched_mirror_pairs", hodmas.FLAG_MIRROR)):
+            if flags and args.no_mirror:
+                continue
+            t = hodmas.autotune(geom, grid, S, "f32", k, flags=hodmas.FLAG_TUNE_BATCH | flags,
+                                cache_path=args.tune_cache)
+            q = hodmas.Plan(geom, grid, S, "f32", max_order=k, tiling=t, flags=flags)
+            direct_ms, replay_ms = time_batch(q, k)
+            qt = q.info().tiling
+            row[name + "_us_per_frame"] = round(direct_ms * 1e3 / n_frames, 3)
+            row[name + "_gpixch_s"] = round(pixch * n_frames / (direct_ms * 1e-3) / 1e9, 2)
+            row[name + "_frac_of_peak"] = round(frac_of_peak(k, pixch * n_frames, direct_ms * 1e-3), 4)
+            row[name + "_graph_replay_us_per_frame"] = round(replay_ms * 1e3 / n_frames, 3)
+            row[name + "_tiling"] = [qt.tile_x, qt.tile_z, qt.split, qt.chunk]
+            q.close()
+        res["per_order"][str(k)] = row
     plan.close()
-    if btm is not None:
-        btm.close()
-        mplan.close()
     print(json.dumps(res))
 
 

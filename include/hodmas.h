@@ -71,7 +71,8 @@ typedef enum {
 #define HODMAS_FLAG_ACC_PLAIN   0x1u  /* plain float32 power sums (default: compensated) */
 #define HODMAS_FLAG_HOST_ONLY   0x2u  /* build host tables only; no device use (inspection) */
 #define HODMAS_FLAG_FORCE_CHECK 0x4u  /* always run the record-boundary test per sample */
-#define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts */
+#define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts,
+                                         timed as a batch runs them */
 #define HODMAS_FLAG_CF          0x10u /* weight each pixel by the coherence factor of its
                                          delayed samples (hodmas_beamform only) */
 #define HODMAS_FLAG_MIRROR      0x20u /* hodmas_beamform and the batch form each pixel
@@ -190,6 +191,10 @@ const char* hodmas_status_string(hodmas_status status);
  * device on a zero record (timing does not depend on sample values).  With a
  * cache_path, results are appended to / looked up in that JSON-lines file,
  * keyed by device architecture and every input that changes the plan.
+ * With HODMAS_FLAG_TUNE_BATCH (and no HODMAS_FLAG_CF) each candidate is timed
+ * the way a batch runs it: copies of the frame, each with its own image, in
+ * one persistent batched launch of up to 256 copies -- enough work units to
+ * fill the device -- and the time per copy is compared.
  * Allocates and frees scratch device memory; not for the hot path.
  * Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED (no candidate could run). */
 hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const hodmas_grid* grid,
@@ -284,16 +289,18 @@ hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
  * present (kind = order x storage type x mirror pairing). */
 hodmas_status hodmas_batch_launch(hodmas_batch_t batch, void* stream);
 
-/* Build (once) a HIP graph holding the persistent kernels of every kind, with
- * no order between them (kinds write disjoint images, so one kind's tail
- * overlaps the next kind's start); they read the work list from device
- * memory, so later hodmas_batch_set calls need no re-capture.
+/* Build (once) a HIP graph holding the persistent kernels of the kinds in the
+ * current work list (every kind when no list is set yet), with no order
+ * between them (kinds write disjoint images, so one kind's tail overlaps the
+ * next kind's start); they read the work list from device memory, so later
+ * hodmas_batch_set calls with those kinds need no re-capture.
  * hodmas_batch_replay launches that graph on `stream`, after fitting the
  * instantiated graph to the current work list: kinds absent from it are
  * switched off and each present kind gets its own LDS size and persistent
- * grid, at most one workgroup per unit.  When that changes a node, the replay
- * first waits for the previous replay of the graph to finish (host-side);
- * replays of an unchanged kind mix do not wait. */
+ * grid, at most one workgroup per unit; a kind the graph has no kernel for
+ * has the graph rebuilt with every kind seen so far.  When that changes a
+ * node, the replay first waits for the previous replay of the graph to
+ * finish (host-side); replays of an unchanged kind mix do not wait. */
 hodmas_status hodmas_batch_capture(hodmas_batch_t batch);
 hodmas_status hodmas_batch_replay(hodmas_batch_t batch, void* stream);
 

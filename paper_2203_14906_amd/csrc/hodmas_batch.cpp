@@ -314,15 +314,20 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
     return HODMAS_OK;
 }
 
-// The graph holds one node per kind and no edges between them: kinds write
-// disjoint images, so one kind's last units overlap the next kind's start
-// instead of the GPU draining between kinds.  Each node reads its unit range
-// from the device header, so later hodmas_batch_set calls need no re-capture.  Before
-// each replay the nodes are fitted to the current work list in the
-// instantiated graph itself: a kind that is absent is switched off (a
-// persistent grid that only finds nothing to do still costs microseconds),
-// and a present kind runs with the LDS its own plans need and the persistent
-// grid that LDS allows, cut to its unit count.
+}  // extern "C"
+
+// The graph holds one node per kind of the work list it was captured for and
+// no edges between them: kinds write disjoint images, so one kind's last
+// units overlap the next kind's start instead of the GPU draining between
+// kinds.  Each node reads its unit range from the device header, so a later
+// hodmas_batch_set with the same kinds (or fewer) needs no re-capture; a set
+// that brings a kind the graph lacks has the graph rebuilt at the next
+// replay, with a node for every kind seen so far.  Nodes are not made for
+// absent kinds: every node of a graph launch costs time even when switched
+// off.  Before each replay the nodes are fitted to the current work list in
+// the instantiated graph itself: a kind that is absent is switched off, and a
+// present kind runs with the LDS its own plans need and the persistent grid
+// that LDS allows, cut to its unit count.
 namespace {
 
 hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, int64_t lds, void** args)
@@ -340,20 +345,23 @@ hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, int
     return kp;
 }
 
-}  // namespace
-
-hodmas_status hodmas_batch_capture(hodmas_batch_t b)
+// (Re)build the graph with a node for every kind in `want`.
+bool build_graph(hodmas_batch_s* b, const bool* want)
 {
-    if (!valid_batch(b))
-        return HODMAS_EINVAL;
-    if (b->exec)
-        return HODMAS_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
     const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(b->d_buf);
     const BatchFrame* frames = reinterpret_cast<const BatchFrame*>(b->d_buf + b->off_frames);
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
     bool ok = hipGraphCreate(&b->graph, 0) == hipSuccess;
     for (int kind = 0; kind < hodmas::kBatchKinds && ok; ++kind) {
+        b->node[kind] = nullptr;
+        b->node_on[kind] = false;
+        if (!want[kind])
+            continue;
         const hipKernelNodeParams kp = node_params(b, kind, b->grid[kind], b->lds_bytes, args);
         hipGraphNode_t node = nullptr;
         ok = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) == hipSuccess;
@@ -368,12 +376,31 @@ hodmas_status hodmas_batch_capture(hodmas_batch_t b)
         ok = hipEventCreateWithFlags(&b->replayed, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
         b->exec = nullptr;
-        return HODMAS_EDEVICE;
+        for (int kind = 0; kind < hodmas::kBatchKinds; ++kind)
+            b->node[kind] = nullptr;
     }
-    return HODMAS_OK;
+    return ok;
+}
+
+}  // namespace
+
+extern "C" {
+
+hodmas_status hodmas_batch_capture(hodmas_batch_t b)
+{
+    if (!valid_batch(b))
+        return HODMAS_EINVAL;
+    if (b->exec)
+        return HODMAS_OK;
+    // the kinds of the current work list, or every kind before any list is set
+    bool want[hodmas::kBatchKinds];
+    for (int kind = 0; kind < hodmas::kBatchKinds; ++kind)
+        want[kind] = !b->has_list || b->end[kind] > b->begin[kind];
+    return build_graph(b, want) ? HODMAS_OK : HODMAS_EDEVICE;
 }
 
 hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
@@ -385,21 +412,33 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
     const BatchUnit* units = reinterpret_cast<const BatchUnit*>(b->d_buf + b->off_units);
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};
     // a launch of `exec` still in flight must not see its nodes change
-    bool change = false;
+    bool change = false, missing = false;
     for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
         const int n = b->end[kind] - b->begin[kind];
+        missing = missing || (n > 0 && !b->node[kind]);
         change = change || (n > 0) != b->node_on[kind] ||
                  (n > 0 && ((int)std::min<int64_t>(b->kind_grid[kind], n) != b->node_grid[kind] ||
                             b->kind_lds[kind] != b->node_lds[kind]));
     }
-    if (change && b->replay_pending) {
+    if ((change || missing) && b->replay_pending) {
         if (hipEventSynchronize(b->replayed) != hipSuccess) {
             (void)hipGetLastError();
             return HODMAS_EDEVICE;
         }
         b->replay_pending = false;
     }
+    if (missing) {
+        // a kind the graph has no node for: rebuild with every kind seen so far
+        bool want[hodmas::kBatchKinds];
+        for (int kind = 0; kind < hodmas::kBatchKinds; ++kind)
+            want[kind] = b->node[kind] != nullptr || b->end[kind] > b->begin[kind];
+        if (!build_graph(b, want))
+            return HODMAS_EDEVICE;
+        change = true;
+    }
     for (int kind = 0; kind < hodmas::kBatchKinds && change; ++kind) {
+        if (!b->node[kind])
+            continue;
         const int n = b->end[kind] - b->begin[kind];
         const bool on = n > 0;
         if (on) {

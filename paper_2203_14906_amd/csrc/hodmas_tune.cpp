@@ -13,6 +13,13 @@
 
 namespace {
 
+// Batch-mode timing: copies of the frame per persistent launch -- enough units
+// (quarter-size tiles as the unit estimate) to fill the device, within an
+// image budget.
+constexpr int64_t kTuneBatchCopies = 256;
+constexpr int64_t kTuneBatchUnits = 8192;
+constexpr size_t kTuneImageBytes = size_t(256) << 20;
+
 std::string tune_key(const char* arch, const hodmas_geometry* g, const hodmas_grid* gr,
                      const hodmas_rf_desc* rf, int32_t order, uint32_t flags)
 {
@@ -27,7 +34,7 @@ std::string tune_key(const char* arch, const hodmas_geometry* g, const hodmas_gr
     }
     char buf[512];
     std::snprintf(buf, sizeof(buf),
-                  "%s|n%d|p%.9g|c%.9g|fs%.9g|t0%.9g|x%016llx|g%dx%d|x0%.9g|dx%.9g|z0%.9g|dz%.9g|"
+                  "%s|v2|n%d|p%.9g|c%.9g|fs%.9g|t0%.9g|x%016llx|g%dx%d|x0%.9g|dx%.9g|z0%.9g|dz%.9g|"
                   "dt%d|S%d|st%lld|k%d|f%u",
                   arch, g->n_elements, g->pitch_m, g->sound_speed_m_s, g->fs_hz, g->t0_s, h, gr->nx,
                   gr->nz, gr->x0_m, gr->dx_m, gr->z0_m, gr->dz_m, rf->dtype, rf->n_samples,
@@ -93,10 +100,22 @@ extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const 
     static const hodmas_tiling kCandidates[] = {
         {16, 16, 1, 64}, {16, 16, 1, 128}, {32, 8, 1, 64},  {8, 32, 1, 64},  {16, 8, 2, 64},
         {8, 8, 4, 64},   {16, 16, 2, 64},  {32, 8, 2, 64},  {32, 16, 1, 64}, {16, 8, 4, 64},
+        {16, 16, 1, 32}, {32, 8, 1, 32},   {16, 4, 4, 64},
     };
+    const bool batch = (flags & HODMAS_FLAG_TUNE_BATCH) && !(flags & HODMAS_FLAG_CF);
     const size_t esz = rf->dtype == HODMAS_F32 ? 4 : 2;
     const size_t rf_bytes = esz * (size_t)rf->channel_stride * (size_t)geometry->n_elements;
     const size_t img_bytes = 4 * (size_t)grid->nx * (size_t)grid->nz;
+    // A batch member is timed the way a batch runs it: enough copies of the
+    // frame in one persistent launch to fill the device (a single small frame
+    // would favour tilings that split elements for parallelism, which a
+    // batch does not need), each copy with its own image.
+    const int64_t tiles_x = (grid->nx + 7) / 8, tiles_z = (grid->nz + 7) / 8;
+    const int copies = batch ? (int)std::max<int64_t>(
+                                   1, std::min<int64_t>({kTuneBatchCopies, kTuneBatchUnits / std::max<int64_t>(
+                                                                               1, tiles_x * tiles_z / 4),
+                                                         (int64_t)(kTuneImageBytes / std::max<size_t>(img_bytes, 1))}))
+                             : 1;
     void* d_rf = nullptr;
     float* d_img = nullptr;
     hipStream_t st = nullptr;
@@ -109,7 +128,7 @@ extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const 
         if (d_img) (void)hipFree(d_img);
     };
     // timing does not depend on sample values: a zero record suffices
-    if (hipMalloc(&d_rf, rf_bytes) != hipSuccess || hipMalloc((void**)&d_img, img_bytes) != hipSuccess ||
+    if (hipMalloc(&d_rf, rf_bytes) != hipSuccess || hipMalloc((void**)&d_img, img_bytes * copies) != hipSuccess ||
         hipMemset(d_rf, 0, rf_bytes) != hipSuccess || hipStreamCreate(&st) != hipSuccess ||
         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         (void)hipGetLastError();
@@ -126,17 +145,39 @@ extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const 
                         &cand, &p) != HODMAS_OK)
             continue;
         bool ok = true;
+        hodmas_batch_t bt = nullptr;
+        if (batch) {
+            hodmas_plan_info pi;
+            ok = hodmas_plan_get_info(p, &pi) == HODMAS_OK &&
+                 hodmas_batch_create(copies, (int64_t)pi.n_tiles * copies, pi.lds_bytes,
+                                     flags & HODMAS_FLAG_ACC_PLAIN, &bt) == HODMAS_OK;
+            if (ok) {
+                std::vector<hodmas_plan_t> plans(copies, p);
+                std::vector<const void*> rfs(copies, d_rf);
+                std::vector<int32_t> orders(copies, order);
+                std::vector<float*> imgs(copies);
+                for (int c = 0; c < copies; ++c)
+                    imgs[c] = d_img + (size_t)c * grid->nx * grid->nz;
+                ok = hodmas_batch_set(bt, plans.data(), rfs.data(), orders.data(), imgs.data(), copies, st) ==
+                     HODMAS_OK;
+            }
+        }
+        auto run = [&]() {
+            return batch ? hodmas_batch_launch(bt, st) == HODMAS_OK
+                         : hodmas_beamform(p, d_rf, order, d_img, st) == HODMAS_OK;
+        };
         for (int w = 0; w < 2 && ok; ++w)
-            ok = hodmas_beamform(p, d_rf, order, d_img, st) == HODMAS_OK;
+            ok = run();
         std::vector<float> times;
         for (int r = 0; r < 5 && ok; ++r) {
-            ok = hipEventRecord(e0, st) == hipSuccess &&
-                 hodmas_beamform(p, d_rf, order, d_img, st) == HODMAS_OK &&
-                 hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            ok = hipEventRecord(e0, st) == hipSuccess && run() && hipEventRecord(e1, st) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.f;
             if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-                times.push_back(ms);
+                times.push_back(ms / copies);
         }
+        if (bt)
+            (void)hodmas_batch_destroy(bt);
         if (ok && hipStreamSynchronize(st) != hipSuccess)
             ok = false;
         hodmas_plan_info inf;

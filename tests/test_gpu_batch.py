@@ -259,3 +259,28 @@ def test_each_kind_gets_its_own_lds_and_grid(hd):
     bt.close()
     big.close()
     small.close()
+
+
+def test_graph_gains_kinds_after_capture(hd):
+    """A graph captured for one kind holds only that kind's kernel; a later
+    work list with other kinds has it rebuilt at the next replay, and every
+    frame still gets its own launch's image (also when the list shrinks back)."""
+    plans, rfs, outs, orders, _ = make_batch_inputs(hd, SPECS, seed0=950)
+    alone = [p.beamform(r, k).clone() for p, r, k in zip(plans, rfs, orders)]
+    batch = hd.Batch(max_frames=16, max_units=100000)
+    first = [0]
+    for step, idx in enumerate([first, list(range(len(SPECS))), first, [len(SPECS) - 1, 1]]):
+        for i in idx:
+            outs[i].fill_(float("nan"))
+        batch.set([plans[i] for i in idx], [rfs[i] for i in idx], [orders[i] for i in idx],
+                  [outs[i] for i in idx])
+        if step == 0:
+            batch.capture()
+        for _ in range(2):
+            batch.replay()
+        torch.cuda.synchronize()
+        for i in idx:
+            assert torch.equal(alone[i], outs[i]), "step %d frame %d" % (step, i)
+    batch.close()
+    for p in plans:
+        p.close()

@@ -83,3 +83,40 @@ def test_autotune_batch_mirror_pairs(tmp_path):
         assert np.array_equal(o.cpu().numpy(), ref)
     bt.close()
     plan.close()
+
+
+def test_batch_tuning_times_batches(tmp_path):
+    """HODMAS_FLAG_TUNE_BATCH times candidates as a batch runs them: on a
+    small grid, where a single frame favours element splits, the tuned tiling
+    runs a many-frame batch at least about as fast as the plan's default."""
+    assert torch.cuda.is_available()
+    from paper_2203_14906_amd import hodmas
+    f = ph.config_frame(1)
+    cache = str(tmp_path / "tune.jsonl")
+    til = hodmas.autotune(f.geometry, f.grid, 1024, "f32", 2, flags=hodmas.FLAG_TUNE_BATCH, cache_path=cache)
+    assert til[0] * til[1] * til[2] == 256
+    rf = torch.from_numpy(ph.to_fp32(f.rf)).cuda()
+    n = 256
+    outs = [torch.empty((f.grid.nz, f.grid.nx), dtype=torch.float32, device="cuda") for _ in range(n)]
+
+    def batch_ms(tiling):
+        plan = hodmas.Plan(f.geometry, f.grid, 1024, "f32", max_order=2, tiling=tiling)
+        bt = hodmas.Batch(max_frames=n, max_units=n * plan.info().n_tiles, max_lds_bytes=plan.info().lds_bytes)
+        bt.set([plan] * n, [rf] * n, [2] * n, outs)
+        ts = []
+        for _ in range(7):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            bt.launch()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        bt.close()
+        plan.close()
+        return sorted(ts)[3]
+
+    default = hodmas.Plan(f.geometry, f.grid, 1024, "f32", max_order=2).info().tiling
+    default = (default.tile_x, default.tile_z, default.split, default.chunk)
+    t_tuned, t_default = batch_ms(til), batch_ms(default)
+    print("batch-tuned %s %.3f ms, default %s %.3f ms" % (til, t_tuned, default, t_default))
+    assert t_tuned <= 1.1 * t_default
