@@ -825,6 +825,17 @@ def bench_display(args, torch):
     npx = grid.nx * grid.nz
     # algorithmic bytes per image: read the image, write envelope and dB image
     algo_bytes = 3 * 4 * npx
+    # the same images through hodmas_display_run_batch (up to 16 per launch pair)
+    for _ in range(args.warmup):
+        disp.run_batch(images, envs, dbs, stream=stream)
+    torch.cuda.synchronize()
+    evb = _events(torch, args.steps)
+    for s in range(args.steps):
+        evb[s][0].record(stream)
+        disp.run_batch(images, envs, dbs, stream=stream)
+        evb[s][1].record(stream)
+    torch.cuda.synchronize()
+    ms_b = sum(a.elapsed_time(b) for a, b in evb) / (args.steps * args.batch)
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import display as D
@@ -844,6 +855,11 @@ def bench_display(args, torch):
            "config": {"workload": "display chain of %d beamformed 512x512 images (128 elements, order 3), "
                                   "2-8 MHz band-pass with 63 taps, 60 dB" % args.batch},
            "us_per_image": round(ms * 1e3, 2),
+           "batched": {"form": "hodmas_display_run_batch, %d images per call (16 per launch pair)" % args.batch,
+                       "us_per_image": round(ms_b * 1e3, 2),
+                       "mpixel_s": round(npx / (ms_b * 1e-3) / 1e6, 1),
+                       "hbm_gb_s": round(algo_bytes / (ms_b * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(algo_bytes / (ms_b * 1e-3) / 1e9 / 8000.0, 4)},
            "roofline": {"bound": "hbm", "achieved": round(algo_bytes / (ms * 1e-3) / 1e9, 1), "peak": 8000.0,
                         "unit": "GB/s", "frac": round(algo_bytes / (ms * 1e-3) / 1e9 / 8000.0, 4),
                         "traffic": None},

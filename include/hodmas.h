@@ -74,7 +74,8 @@ typedef enum {
 #define HODMAS_FLAG_TUNE_BATCH  0x8u  /* hodmas_autotune: only tilings a batch accepts,
                                          timed as a batch runs them */
 #define HODMAS_FLAG_CF          0x10u /* weight each pixel by the coherence factor of its
-                                         delayed samples (hodmas_beamform only) */
+                                         delayed samples (hodmas_beamform and the batch
+                                         form; not hodmas_beamform_orders) */
 #define HODMAS_FLAG_MIRROR      0x20u /* hodmas_beamform and the batch form each pixel
                                          together with its mirror image about x = 0 from
                                          one delay (symmetric array and grid only, see
@@ -191,7 +192,8 @@ const char* hodmas_status_string(hodmas_status status);
  * device on a zero record (timing does not depend on sample values).  With a
  * cache_path, results are appended to / looked up in that JSON-lines file,
  * keyed by device architecture and every input that changes the plan.
- * With HODMAS_FLAG_TUNE_BATCH (and no HODMAS_FLAG_CF) each candidate is timed
+ * With HODMAS_FLAG_TUNE_BATCH (unless HODMAS_FLAG_CF comes with
+ * HODMAS_FLAG_ACC_PLAIN, which no batch runs) each candidate is timed
  * the way a batch runs it: copies of the frame, each with its own image, in
  * one persistent batched launch of up to 256 copies -- enough work units to
  * fill the device -- and the time per copy is compared.
@@ -275,12 +277,15 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
  * at orders[f] from rf[f] (device) into images[f] (device float32 [nz][nx]).
  * Host arrays of n_frames entries, read during the call.  The work list is
  * copied to the device asynchronously on `stream` (launches on the same stream
- * see it).  A HODMAS_FLAG_MIRROR plan's frame runs as mirror pairs, as in
- * hodmas_beamform, with the same image bit for bit.  Errors: EINVAL (null
- * entries, order outside the plan, HODMAS_FLAG_CF -- which the batch kernels
- * do not carry -- or an accumulation flag other than the batch's, host-only
- * or other-device plan, too many frames/units, plan LDS above the batch's
- * bound or a workgroup other than 256 threads), EUNSUPPORTED, EDEVICE. */
+ * see it).  A HODMAS_FLAG_MIRROR plan's frame runs as mirror pairs, and a
+ * HODMAS_FLAG_CF plan's frame with coherence-factor weighting (Sec. VI), as
+ * in hodmas_beamform, with the same image bit for bit.  Errors: EINVAL (null
+ * entries, order outside the plan, an accumulation flag other than the
+ * batch's, host-only or other-device plan, too many frames/units, plan LDS
+ * above the batch's bound or a workgroup other than 256 threads),
+ * EUNSUPPORTED (order above 6; a HODMAS_FLAG_CF plan in a batch created with
+ * HODMAS_FLAG_ACC_PLAIN -- the weighted kinds accumulate compensated),
+ * EDEVICE. */
 hodmas_status hodmas_batch_set(hodmas_batch_t batch, const hodmas_plan_t* plans,
                                const void* const* rf, const int32_t* orders,
                                float* const* images, int32_t n_frames, void* stream);
@@ -365,6 +370,16 @@ hodmas_status hodmas_display_plan(const hodmas_display_desc* desc, hodmas_displa
  * input), EDEVICE. */
 hodmas_status hodmas_display_run(hodmas_display_t display, const float* image_dev, float* envelope_dev,
                                  float* db_dev, void* stream);
+
+/* The display chain of n images of the plan's shape in as few launches as
+ * possible: up to 16 images per launch pair, each image's own maximum for its
+ * dB scale (results equal n hodmas_display_run calls bit for bit).  Host
+ * arrays of n device pointers; envelopes_dev may be NULL (no envelopes) or
+ * hold NULL entries.  Errors: EINVAL (as for hodmas_display_run, per image;
+ * n < 1), EDEVICE. */
+hodmas_status hodmas_display_run_batch(hodmas_display_t display, const float* const* images_dev,
+                                       float* const* envelopes_dev, float* const* dbs_dev, int32_t n,
+                                       void* stream);
 
 /* Release a display plan.  NULL is accepted. */
 hodmas_status hodmas_display_destroy(hodmas_display_t display);

@@ -1,5 +1,5 @@
 // Batched form: a work list of (frame, tile) units over many frames, grouped by
-// kind (order x storage type x mirror pairing) and walked by one persistent
+// kind (order x storage type x mirror pairing x coherence weighting) and walked by one persistent
 // kernel per kind; a HIP graph holds the kernels so one graph launch runs the
 // batch.
 #include <hip/hip_runtime_api.h>
@@ -23,6 +23,7 @@ constexpr size_t kAlign = 256;
 // Estimated VALU slots per pixel-element by order (delay, gather, root, sums):
 // only used to order the work list, heaviest units first.
 constexpr int64_t kSlots[7] = {0, 19, 25, 32, 32, 36, 38};
+constexpr int64_t kCfSlots = 4;   // coherence weighting: two more compensated sums
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -122,8 +123,9 @@ hodmas_status hodmas_batch_create(int32_t max_frames, int64_t max_units, int64_t
     }
     int max_grid = 0;
     for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
-        const void* fn = hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
-                                              hodmas::kind_pairing(kind), comp);
+        const void* fn = hodmas::batch_kernel(kind, comp);
+        if (!fn)
+            continue;   // no such kind under this accumulation mode
         if (b->lds_bytes > 64 * 1024 &&
             hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) != hipSuccess) {
             (void)hipGetLastError();
@@ -184,10 +186,13 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
             const hodmas_plan_s* p = plans[f];
             if (!p || p->magic != hodmas::kPlanMagic || !rf[f] || !images[f])
                 return HODMAS_EINVAL;
-            if ((p->flags & (HODMAS_FLAG_HOST_ONLY | HODMAS_FLAG_CF)) || p->device != b->device)
-                return HODMAS_EINVAL;   // no coherence weighting in the batch kernels
+            if ((p->flags & HODMAS_FLAG_HOST_ONLY) || p->device != b->device)
+                return HODMAS_EINVAL;
             if ((p->flags & HODMAS_FLAG_ACC_PLAIN) != (b->flags & HODMAS_FLAG_ACC_PLAIN))
                 return HODMAS_EINVAL;
+            const int cf = (p->flags & HODMAS_FLAG_CF) ? 1 : 0;
+            if (cf && (b->flags & HODMAS_FLAG_ACC_PLAIN))
+                return HODMAS_EUNSUPPORTED;   // coherence-weighted kinds accumulate compensated
             if (orders[f] < 1 || orders[f] > p->max_order)
                 return HODMAS_EUNSUPPORTED;
             if (p->lds_bytes > b->lds_bytes)
@@ -201,7 +206,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
             if ((int64_t)units.size() + n_units > b->max_units)
                 return HODMAS_EINVAL;
             pixch += int64_t(p->grid.nx) * p->grid.nz * p->geom.n_elements;
-            const int kind = hodmas::batch_kind(orders[f], p->rf.dtype, pairing);
+            const int kind = hodmas::batch_kind(orders[f], p->rf.dtype, pairing, cf);
             kl[kind] = std::max(kl[kind], p->lds_bytes);
             for (int i = 0; i < n_units; ++i) {
                 const int t = pairing == 1 ? i : i / half * 2 * half + i % half;
@@ -209,7 +214,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
                 const int64_t pix = int64_t(td.nx) * td.nz;
                 int64_t cost = pix;  // zero-fill only
                 if (td.n_active >= orders[f])
-                    cost = td.n_active * (pix * kSlots[orders[f]] + int64_t(td.window) * 2);
+                    cost = td.n_active * (pix * (kSlots[orders[f]] + kCfSlots * cf) + int64_t(td.window) * 2);
                 units.push_back(Unit{cost, kind, f, (int32_t)t});
             }
         }
@@ -225,8 +230,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
         if (kl[kind] == 0)
             continue;
         if (b->occ_lds[kind] != kl[kind]) {
-            const void* fn = hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
-                                                  hodmas::kind_pairing(kind), comp);
+            const void* fn = hodmas::batch_kernel(kind, comp);
             int per_cu = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, hodmas::kBlock, (size_t)kl[kind]) !=
                     hipSuccess || per_cu < 1) {
@@ -301,8 +305,7 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
         if (b->end[kind] <= b->begin[kind])
             continue;
         const int grid = (int)std::min<int64_t>(b->kind_grid[kind], b->end[kind] - b->begin[kind]);
-        if (hodmas::launch_batch(hodmas::kind_order(kind), hodmas::kind_dtype(kind), hodmas::kind_pairing(kind),
-                                 hdr, frames, units, grid, comp, b->kind_lds[kind], stream) != 0) {
+        if (hodmas::launch_batch(kind, hdr, frames, units, grid, comp, b->kind_lds[kind], stream) != 0) {
             (void)hipGetLastError();
             return HODMAS_EDEVICE;
         }
@@ -334,9 +337,7 @@ hipKernelNodeParams node_params(const hodmas_batch_s* b, int kind, int grid, int
 {
     hipKernelNodeParams kp;
     std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void*>(hodmas::batch_kernel(hodmas::kind_order(kind), hodmas::kind_dtype(kind),
-                                                     hodmas::kind_pairing(kind),
-                                                     !(b->flags & HODMAS_FLAG_ACC_PLAIN)));
+    kp.func = const_cast<void*>(hodmas::batch_kernel(kind, !(b->flags & HODMAS_FLAG_ACC_PLAIN)));
     kp.gridDim = dim3(grid);
     kp.blockDim = dim3(hodmas::kBlock);
     kp.sharedMemBytes = (unsigned)lds;
@@ -360,8 +361,8 @@ bool build_graph(hodmas_batch_s* b, const bool* want)
     for (int kind = 0; kind < hodmas::kBatchKinds && ok; ++kind) {
         b->node[kind] = nullptr;
         b->node_on[kind] = false;
-        if (!want[kind])
-            continue;
+        if (!want[kind] || !hodmas::batch_kernel(kind, !(b->flags & HODMAS_FLAG_ACC_PLAIN)))
+            continue;   // not wanted, or no such kind under this accumulation mode
         const hipKernelNodeParams kp = node_params(b, kind, b->grid[kind], b->lds_bytes, args);
         hipGraphNode_t node = nullptr;
         ok = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) == hipSuccess;

@@ -34,14 +34,23 @@ __device__ __forceinline__ int bit_reverse(int i, int log2n)
     return (int)(__builtin_bitreverse32((uint32_t)i) >> (32 - log2n));
 }
 
-__global__ __launch_bounds__(kDispBlock) void envelope_kernel(const float* __restrict__ image,
-                                                              float* __restrict__ env, int nx, int nz,
-                                                              int log2n, int cols,
-                                                              const float* __restrict__ taps, int numtaps,
-                                                              const float2* __restrict__ tw,
-                                                              float* __restrict__ block_max)
+// Images of one launch: the envelope kernel and the log compression take
+// image blockIdx.y (up to kDisplayBatch per launch pair).
+constexpr int kDisplayBatch = 16;
+struct DisplayImages {
+    const float* image[kDisplayBatch];
+    float* env[kDisplayBatch];        // envelope out (the dB buffer when no envelope is wanted)
+    float* db[kDisplayBatch];
+};
+
+__global__ __launch_bounds__(kDispBlock) void envelope_kernel(DisplayImages ims, int nx, int nz, int log2n,
+                                                              int cols, const float* __restrict__ taps,
+                                                              int numtaps, const float2* __restrict__ tw,
+                                                              float* __restrict__ block_max, int n_blocks)
 {
     extern __shared__ float lds[];
+    const float* __restrict__ image = ims.image[blockIdx.y];
+    float* __restrict__ env = ims.env[blockIdx.y];
     // column c at c * ld: the odd stride keeps the row-by-row transposing
     // passes free of bank conflicts
     const int ld = nz + 1;
@@ -146,16 +155,18 @@ __global__ __launch_bounds__(kDispBlock) void envelope_kernel(const float* __res
         float bm = 0.f;
         for (int w = 0; w < kDispBlock / 64; ++w)
             bm = fmaxf(bm, lds[w]);
-        block_max[blockIdx.x] = bm;
+        block_max[(int64_t)blockIdx.y * n_blocks + blockIdx.x] = bm;
     }
 }
 
-__global__ __launch_bounds__(kDispBlock) void log_compress_kernel(const float* __restrict__ env,
-                                                                  float* __restrict__ db, int64_t count,
+__global__ __launch_bounds__(kDispBlock) void log_compress_kernel(DisplayImages ims, int64_t count,
                                                                   const float* __restrict__ block_max,
                                                                   int n_blocks, float dyn_range_db)
 {
     __shared__ float part[kDispBlock / 64];
+    const float* env = ims.env[blockIdx.y];
+    float* db = ims.db[blockIdx.y];
+    block_max += (int64_t)blockIdx.y * n_blocks;
     float m = 0.f;
     for (int i = threadIdx.x; i < n_blocks; i += kDispBlock)
         m = fmaxf(m, block_max[i]);
@@ -307,7 +318,7 @@ hodmas_status hodmas_display_plan(const hodmas_display_desc* d, hodmas_display_t
                                    (int)lds) == hipSuccess) &&
               hipMalloc((void**)&p->d_taps, sizeof(float) * ft.size()) == hipSuccess &&
               hipMalloc((void**)&p->d_tw, sizeof(float2) * tw.size()) == hipSuccess &&
-              hipMalloc((void**)&p->d_block_max, sizeof(float) * p->n_blocks) == hipSuccess &&
+              hipMalloc((void**)&p->d_block_max, sizeof(float) * p->n_blocks * kDisplayBatch) == hipSuccess &&
               hipMemcpy(p->d_taps, ft.data(), sizeof(float) * ft.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(p->d_tw, tw.data(), sizeof(float2) * tw.size(), hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
@@ -319,34 +330,71 @@ hodmas_status hodmas_display_plan(const hodmas_display_desc* d, hodmas_display_t
     return HODMAS_OK;
 }
 
-hodmas_status hodmas_display_run(hodmas_display_t p, const float* image_dev, float* envelope_dev, float* db_dev,
-                                 void* stream)
+}  // extern "C"
+
+namespace {
+
+// Launch the chain for n <= kDisplayBatch images of one shape.
+hipError_t launch_display(const hodmas_display_desc& d, int log2n, int cols, int n_blocks, const float* taps,
+                          const float2* tw, float* block_max, const DisplayImages& ims, int n, hipStream_t st)
 {
-    if (!p || p->magic != kDisplayMagic || !image_dev || !db_dev || image_dev == db_dev ||
-        image_dev == envelope_dev)
+    const size_t lds = sizeof(float) * 2 * (size_t)cols * (d.nz + 1);
+    hipLaunchKernelGGL(envelope_kernel, dim3(n_blocks, n), dim3(kDispBlock), lds, st, ims, d.nx, d.nz, log2n,
+                       cols, taps, d.numtaps, tw, block_max, n_blocks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        const int64_t count = (int64_t)d.nx * d.nz;
+        const int grid = (int)std::min<int64_t>((count + kDispBlock - 1) / kDispBlock, 4096);
+        hipLaunchKernelGGL(log_compress_kernel, dim3(grid, n), dim3(kDispBlock), 0, st, ims, count, block_max,
+                           n_blocks, d.dynamic_range_db);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+hodmas_status hodmas_display_run_batch(hodmas_display_t p, const float* const* images_dev,
+                                       float* const* envelopes_dev, float* const* dbs_dev, int32_t n,
+                                       void* stream)
+{
+    if (!p || p->magic != kDisplayMagic || !images_dev || !dbs_dev || n < 1)
         return HODMAS_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        const float* env = envelopes_dev ? envelopes_dev[i] : nullptr;
+        if (!images_dev[i] || !dbs_dev[i] || images_dev[i] == dbs_dev[i] || images_dev[i] == env)
+            return HODMAS_EINVAL;
+    }
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess)
         return HODMAS_EDEVICE;
     if (cur != p->device && hipSetDevice(p->device) != hipSuccess)
         return HODMAS_EDEVICE;
-    const hodmas_display_desc& d = p->desc;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    float* env = envelope_dev ? envelope_dev : db_dev;     // the dB pass then works in place
-    const size_t lds = sizeof(float) * 2 * (size_t)p->cols * (d.nz + 1);
-    hipLaunchKernelGGL(envelope_kernel, dim3(p->n_blocks), dim3(kDispBlock), lds, st, image_dev, env, d.nx,
-                       d.nz, p->log2n, p->cols, p->d_taps, d.numtaps, p->d_tw, p->d_block_max);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        const int64_t count = (int64_t)d.nx * d.nz;
-        const int grid = (int)std::min<int64_t>((count + kDispBlock - 1) / kDispBlock, 4096);
-        hipLaunchKernelGGL(log_compress_kernel, dim3(grid), dim3(kDispBlock), 0, st, env, db_dev, count,
-                           p->d_block_max, p->n_blocks, d.dynamic_range_db);
-        e = hipGetLastError();
+    hipError_t e = hipSuccess;
+    for (int32_t i0 = 0; i0 < n && e == hipSuccess; i0 += kDisplayBatch) {
+        const int m = std::min<int32_t>(kDisplayBatch, n - i0);
+        DisplayImages ims{};
+        for (int j = 0; j < m; ++j) {
+            float* env = envelopes_dev ? envelopes_dev[i0 + j] : nullptr;
+            ims.image[j] = images_dev[i0 + j];
+            ims.db[j] = dbs_dev[i0 + j];
+            ims.env[j] = env ? env : dbs_dev[i0 + j];     // the dB pass then works in place
+        }
+        e = launch_display(p->desc, p->log2n, p->cols, p->n_blocks, p->d_taps, p->d_tw, p->d_block_max, ims, m,
+                           st);
     }
     if (cur != p->device)
         (void)hipSetDevice(cur);
     return e == hipSuccess ? HODMAS_OK : HODMAS_EDEVICE;
+}
+
+hodmas_status hodmas_display_run(hodmas_display_t p, const float* image_dev, float* envelope_dev, float* db_dev,
+                                 void* stream)
+{
+    return hodmas_display_run_batch(p, &image_dev, envelope_dev ? &envelope_dev : nullptr, &db_dev, 1, stream);
 }
 
 }  // extern "C"
@@ -438,19 +486,12 @@ hodmas_status hodmas_display_run_static(const hodmas_display_desc* d, const floa
     hipLaunchKernelGGL(static_tables_kernel, dim3((n_tab + kDispBlock - 1) / kDispBlock), dim3(kDispBlock), 0, st,
                        ft, d->numtaps, d->nz, d_taps, d_tw);
     hipError_t e = hipGetLastError();
-    float* env = envelope_dev ? envelope_dev : db_dev;
     if (e == hipSuccess) {
-        const size_t lds = sizeof(float) * 2 * (size_t)cols * (d->nz + 1);
-        hipLaunchKernelGGL(envelope_kernel, dim3(n_blocks), dim3(kDispBlock), lds, st, image_dev, env, d->nx,
-                           d->nz, log2n, cols, d_taps, d->numtaps, d_tw, d_block_max);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-        const int64_t count = (int64_t)d->nx * d->nz;
-        const int grid = (int)std::min<int64_t>((count + kDispBlock - 1) / kDispBlock, 4096);
-        hipLaunchKernelGGL(log_compress_kernel, dim3(grid), dim3(kDispBlock), 0, st, env, db_dev, count,
-                           d_block_max, n_blocks, d->dynamic_range_db);
-        e = hipGetLastError();
+        DisplayImages ims{};
+        ims.image[0] = image_dev;
+        ims.db[0] = db_dev;
+        ims.env[0] = envelope_dev ? envelope_dev : db_dev;
+        e = launch_display(*d, log2n, cols, n_blocks, d_taps, d_tw, d_block_max, ims, 1, st);
     }
     return e == hipSuccess ? HODMAS_OK : HODMAS_EDEVICE;
 }

@@ -40,15 +40,20 @@ struct OrderImages {
 };
 
 // Work list of the persistent batched kernels (device memory).  Units are
-// grouped by kind = (order, storage type, pixels per delay: 1, or 2 for mirror
-// pairs); kind k owns units [begin[k], end[k]).
-constexpr int kBatchKinds = HODMAS_MAX_ORDER * 3 * 2;
-constexpr int batch_kind(int order, int dtype, int pairing) { return ((order - 1) * 3 + dtype) * 2 + pairing - 1; }
-constexpr int kind_order(int kind) { return kind / 6 + 1; }
+// grouped by kind = (coherence weighting, order, storage type, pixels per
+// delay: 1, or 2 for mirror pairs); kind k owns units [begin[k], end[k]).
+constexpr int kBatchKinds = 2 * HODMAS_MAX_ORDER * 3 * 2;
+constexpr int batch_kind(int order, int dtype, int pairing, int cf)
+{
+    return ((cf * HODMAS_MAX_ORDER + order - 1) * 3 + dtype) * 2 + pairing - 1;
+}
+constexpr int kind_order(int kind) { return kind / 6 % HODMAS_MAX_ORDER + 1; }
 constexpr int kind_dtype(int kind) { return kind / 2 % 3; }
 constexpr int kind_pairing(int kind) { return kind % 2 + 1; }
-static_assert(batch_kind(kind_order(kBatchKinds - 1), kind_dtype(kBatchKinds - 1),
-                         kind_pairing(kBatchKinds - 1)) == kBatchKinds - 1,
+constexpr int kind_cf(int kind) { return kind / (6 * HODMAS_MAX_ORDER); }
+static_assert(batch_kind(kind_order(kBatchKinds - 1), kind_dtype(kBatchKinds - 1), kind_pairing(kBatchKinds - 1),
+                         kind_cf(kBatchKinds - 1)) == kBatchKinds - 1 &&
+                  batch_kind(kind_order(40), kind_dtype(40), kind_pairing(40), kind_cf(40)) == 40,
               "kind decoding");
 
 constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
@@ -116,9 +121,11 @@ FrameArgs frame_args(const hodmas_plan_s* plan, const void* rf_dev, float* image
 int launch_orders(const FrameArgs& a, const OrderImages& out, int kmax, int dtype, bool compensated,
                   int64_t lds_bytes, void* stream);
 
-// The persistent batched kernel of one kind (for graph nodes) and a launch of it.
-const void* batch_kernel(int order, int dtype, int pairing, bool compensated);
-int launch_batch(int order, int dtype, int pairing, const BatchHeader* hdr, const BatchFrame* frames,
-                 const BatchUnit* units, int grid, bool compensated, int64_t lds_bytes, void* stream);
+// The persistent batched kernel of one kind (for graph nodes) and a launch of
+// it.  Coherence-weighted kinds exist for compensated accumulation only
+// (batch_kernel returns null for the others).
+const void* batch_kernel(int kind, bool compensated);
+int launch_batch(int kind, const BatchHeader* hdr, const BatchFrame* frames, const BatchUnit* units, int grid,
+                 bool compensated, int64_t lds_bytes, void* stream);
 
 }  // namespace hodmas

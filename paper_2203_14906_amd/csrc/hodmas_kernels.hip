@@ -578,7 +578,8 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
     }
 }
 
-// Persistent form: one kernel per (order, storage type, pairing).  Its fixed
+// Persistent form: one kernel per (order, storage type, pairing, coherence
+// weighting).  Its fixed
 // grid walks that kind's slice of the batch's work list -- (frame, tile) units
 // of many frames with their own plans, sorted by estimated cost -- with
 // workgroup b taking units b, 2G-1-b, 2G+b, ... (a snake, which evens out the
@@ -591,13 +592,13 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 // costs a few spills per staged chunk, none in the element loop.
 constexpr int batch_min_waves(int K, int M) { return M == 2 && K >= 4 ? 6 : 1; }
 
-template <int K, int DT, bool COMP, int M>
+template <int K, int DT, bool COMP, bool CF, int M>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_min_waves(K, M))))
 void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr, const BatchFrame* __restrict__ frames,
                          const BatchUnit* __restrict__ units)
 {
     extern __shared__ float lds[];
-    constexpr int kind = batch_kind(K, DT, M);
+    constexpr int kind = batch_kind(K, DT, M, CF ? 1 : 0);
     const BatchHeader h = load_const(hdr, 0);
     const int first = h.begin[kind];
     const int n = h.end[kind] - first;
@@ -608,7 +609,7 @@ void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr, const BatchFrame* 
             continue;
         const BatchUnit un = load_const(units, first + u);
         const BatchFrame fr = load_const(frames, un.frame);
-        process_tile<K, DT, COMP, false, M>(fr.args, un.tile, lds);
+        process_tile<K, DT, COMP, CF, M>(fr.args, un.tile, lds);
     }
 }
 
@@ -985,34 +986,37 @@ int launch_frame(const FrameArgs& a, int order, int dtype, bool compensated, boo
     return (int)hipErrorInvalidValue;
 }
 
+// coherence-weighted kinds exist for compensated accumulation only
 template <int K, int DT, int M>
-const void* batch_fn(bool comp)
+const void* batch_fn(bool comp, bool cf)
 {
-    return comp ? reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, true, M>)
-                : reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, false, M>);
+    if (cf)
+        return comp ? reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, true, true, M>) : nullptr;
+    return comp ? reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, true, false, M>)
+                : reinterpret_cast<const void*>(&hodmas_batch_kernel<K, DT, false, false, M>);
 }
 
 template <int DT, int M>
-const void* batch_fn_dt(int order, bool comp)
+const void* batch_fn_dt(int order, bool comp, bool cf)
 {
     switch (order) {
-    case 1: return batch_fn<1, DT, M>(comp);
-    case 2: return batch_fn<2, DT, M>(comp);
-    case 3: return batch_fn<3, DT, M>(comp);
-    case 4: return batch_fn<4, DT, M>(comp);
-    case 5: return batch_fn<5, DT, M>(comp);
-    case 6: return batch_fn<6, DT, M>(comp);
+    case 1: return batch_fn<1, DT, M>(comp, cf);
+    case 2: return batch_fn<2, DT, M>(comp, cf);
+    case 3: return batch_fn<3, DT, M>(comp, cf);
+    case 4: return batch_fn<4, DT, M>(comp, cf);
+    case 5: return batch_fn<5, DT, M>(comp, cf);
+    case 6: return batch_fn<6, DT, M>(comp, cf);
     }
     return nullptr;
 }
 
 template <int M>
-const void* batch_fn_m(int order, int dtype, bool comp)
+const void* batch_fn_m(int order, int dtype, bool comp, bool cf)
 {
     switch (dtype) {
-    case HODMAS_F32: return batch_fn_dt<HODMAS_F32, M>(order, comp);
-    case HODMAS_F16: return batch_fn_dt<HODMAS_F16, M>(order, comp);
-    case HODMAS_I16: return batch_fn_dt<HODMAS_I16, M>(order, comp);
+    case HODMAS_F32: return batch_fn_dt<HODMAS_F32, M>(order, comp, cf);
+    case HODMAS_F16: return batch_fn_dt<HODMAS_F16, M>(order, comp, cf);
+    case HODMAS_I16: return batch_fn_dt<HODMAS_I16, M>(order, comp, cf);
     }
     return nullptr;
 }
@@ -1029,19 +1033,23 @@ int launch_orders(const FrameArgs& a, const OrderImages& out, int kmax, int dtyp
     return (int)hipErrorInvalidValue;
 }
 
-const void* batch_kernel(int order, int dtype, int pairing, bool compensated)
+const void* batch_kernel(int kind, bool compensated)
 {
-    switch (pairing) {
-    case 1: return batch_fn_m<1>(order, dtype, compensated);
-    case 2: return batch_fn_m<2>(order, dtype, compensated);
+    if (kind < 0 || kind >= kBatchKinds)
+        return nullptr;
+    const int order = kind_order(kind), dtype = kind_dtype(kind);
+    const bool cf = kind_cf(kind) != 0;
+    switch (kind_pairing(kind)) {
+    case 1: return batch_fn_m<1>(order, dtype, compensated, cf);
+    case 2: return batch_fn_m<2>(order, dtype, compensated, cf);
     }
     return nullptr;
 }
 
-int launch_batch(int order, int dtype, int pairing, const BatchHeader* hdr, const BatchFrame* frames,
-                 const BatchUnit* units, int grid, bool compensated, int64_t lds_bytes, void* stream)
+int launch_batch(int kind, const BatchHeader* hdr, const BatchFrame* frames, const BatchUnit* units, int grid,
+                 bool compensated, int64_t lds_bytes, void* stream)
 {
-    const void* fn = batch_kernel(order, dtype, pairing, compensated);
+    const void* fn = batch_kernel(kind, compensated);
     if (!fn)
         return (int)hipErrorInvalidValue;
     void* args[] = {(void*)&hdr, (void*)&frames, (void*)&units};

@@ -102,7 +102,9 @@ extern "C" hodmas_status hodmas_autotune(const hodmas_geometry* geometry, const 
         {8, 8, 4, 64},   {16, 16, 2, 64},  {32, 8, 2, 64},  {32, 16, 1, 64}, {16, 8, 4, 64},
         {16, 16, 1, 32}, {32, 8, 1, 32},   {16, 4, 4, 64},
     };
-    const bool batch = (flags & HODMAS_FLAG_TUNE_BATCH) && !(flags & HODMAS_FLAG_CF);
+    // (coherence-weighted batch kinds exist for compensated sums only)
+    const bool batch = (flags & HODMAS_FLAG_TUNE_BATCH) &&
+                       !((flags & HODMAS_FLAG_CF) && (flags & HODMAS_FLAG_ACC_PLAIN));
     const size_t esz = rf->dtype == HODMAS_F32 ? 4 : 2;
     const size_t rf_bytes = esz * (size_t)rf->channel_stride * (size_t)geometry->n_elements;
     const size_t img_bytes = 4 * (size_t)grid->nx * (size_t)grid->nz;

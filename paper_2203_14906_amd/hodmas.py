@@ -171,6 +171,8 @@ def _load():
     L.hodmas_display_run.argtypes = [vp, vp, vp, vp, vp]
     L.hodmas_display_destroy.restype = i32
     L.hodmas_display_destroy.argtypes = [vp]
+    L.hodmas_display_run_batch.restype = i32
+    L.hodmas_display_run_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
     L.hodmas_display_run_static.restype = i32
     L.hodmas_display_run_static.argtypes = [ctypes.POINTER(DisplayDesc), vp, vp, vp, vp]
     L.hodmas_image_metrics.restype = i32
@@ -459,6 +461,28 @@ class Display:
                                       ctypes.c_void_p(db.data_ptr()), _stream_handle(stream)),
                "hodmas_display_run")
         return envelope, db
+
+    def run_batch(self, images, envelopes=None, dbs=None, stream=None):
+        """The chain over a list of images of this shape (up to 16 per launch
+        pair).  Returns (envelopes or None, dB images); allocates the dB
+        images not given."""
+        import torch
+        n = len(images)
+        if n < 1 or (envelopes is not None and len(envelopes) != n) or (dbs is not None and len(dbs) != n):
+            raise ValueError("images, envelopes and dbs must be non-empty lists of one length")
+        if dbs is None:
+            dbs = [torch.empty_like(im) for im in images]
+        for t in list(images) + list(dbs) + list(envelopes or []):
+            if t is not None and (t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous()
+                                  or tuple(t.shape) != (self.nz, self.nx)):
+                raise ValueError("images must be contiguous float32 GPU tensors [nz][nx]")
+        arr = ctypes.c_void_p * n
+        pi = arr(*[im.data_ptr() for im in images])
+        pd = arr(*[d.data_ptr() for d in dbs])
+        pe = arr(*[(e.data_ptr() if e is not None else None) for e in envelopes]) if envelopes is not None else None
+        _check(lib.hodmas_display_run_batch(self._h, pi, pe, pd, n, _stream_handle(stream)),
+               "hodmas_display_run_batch")
+        return envelopes, dbs
 
     @property
     def handle(self):

@@ -15,8 +15,8 @@
 namespace hodmas {
 int launch_frame(const FrameArgs&, int, int, bool, bool, bool, int64_t, void*) { std::abort(); }
 int launch_orders(const FrameArgs&, const OrderImages&, int, int, bool, int64_t, void*) { std::abort(); }
-const void* batch_kernel(int, int, int, bool) { std::abort(); }
-int launch_batch(int, int, int, const BatchHeader*, const BatchFrame*, const BatchUnit*, int, bool, int64_t, void*)
+const void* batch_kernel(int, bool) { std::abort(); }
+int launch_batch(int, const BatchHeader*, const BatchFrame*, const BatchUnit*, int, bool, int64_t, void*)
 {
     std::abort();
 }

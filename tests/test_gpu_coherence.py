@@ -1,7 +1,7 @@
-"""Coherence-factor weighting in the per-frame kernel against the FP64 oracle
-(same stored values): relative L2 within 1e-5 for FP32 storage and 2e-5 on
-the same stored values for FP16 / int16, plus the exact constant-channel cases
-and the entry points that refuse weighted plans."""
+"""Coherence-factor weighting in the per-frame and batched kernels against the
+FP64 oracle (same stored values): relative L2 within 1e-5 for FP32 storage
+and 2e-5 on the same stored values for FP16 / int16, plus the exact
+constant-channel cases and the entry points that refuse weighted plans."""
 import ctypes
 import sys
 
@@ -99,9 +99,63 @@ def test_constant_channels_and_refusals(hd):
     rf = torch.from_numpy(same).cuda()
     assert hd.lib.hodmas_beamform_orders(wplan.handle, ctypes.c_void_p(rf.data_ptr()), 2, ptrs, None) == \
         hd.EUNSUPPORTED
-    batch = hd.Batch(max_frames=2, max_units=1000)
-    with pytest.raises(hd.HodmasError):
-        batch.set([wplan], [rf], [1], [out])
+    # the weighted batch kinds accumulate compensated: a plain-accumulation
+    # batch refuses a weighted plan
+    pplan = hd.Plan(geom, grid, S, "f32", max_order=4, tiling=(16, 16, 1, 0), flags=hd.FLAG_CF | hd.FLAG_ACC_PLAIN)
+    batch = hd.Batch(max_frames=2, max_units=1000, flags=hd.FLAG_ACC_PLAIN)
+    with pytest.raises(hd.HodmasError) as ei:
+        batch.set([pplan], [rf], [1], [out])
+    assert ei.value.status == hd.EUNSUPPORTED
     batch.close()
+    pplan.close()
     wplan.close()
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "i16"])
+def test_weighted_plans_in_the_batch(hd, dtype):
+    """Coherence-weighted plans (unpaired and mirror-paired) mixed with
+    unweighted ones of several orders in one batch: every image equals the
+    frame's own hodmas_beamform launch bit for bit (direct launch and graph
+    replays), and the weighted images match the oracle's weighted image."""
+    sym = ph.Grid(nx=64, nz=53, x0_m=-(64 - 1) / 2.0 * 0.17e-3, dx_m=0.17e-3, z0_m=0.2e-3, dz_m=0.21e-3)
+    ragged = ph.Grid(nx=37, nz=53, x0_m=-3e-3, dx_m=0.17e-3, z0_m=0.2e-3, dz_m=0.21e-3)
+    # (elements, seed, grid, flags, order): weighted frames from the per-frame tests' phantoms
+    specs = [(13, 17, ragged, hd.FLAG_CF, 6), (16, 9, sym, hd.FLAG_CF | hd.FLAG_MIRROR, 3),
+             (13, 17, ragged, 0, 6), (16, 9, sym, hd.FLAG_CF | hd.FLAG_MIRROR, 1),
+             (13, 17, ragged, hd.FLAG_CF, 2), (16, 9, sym, hd.FLAG_MIRROR, 6)]
+    plans, devs, data, outs, orders = [], [], [], [], []
+    for n_el, seed, grid, flags, k in specs:
+        f = ph.make_frame(n_el, 300, grid.nx, grid.nz, n_points=6, n_lines=1, snr_db=15.0, seed=seed)
+        arr, scale = stored(f.rf, dtype, seed=seed)
+        plans.append(hd.Plan(f.geometry, grid, 300, dtype, max_order=6, dequant_scale=scale, flags=flags,
+                             tiling=(16, 16, 1, 8)))
+        devs.append(torch.from_numpy(np.ascontiguousarray(arr)).cuda())
+        data.append((f, arr, scale, grid))
+        outs.append(torch.full((grid.nz, grid.nx), float("nan"), dtype=torch.float32, device="cuda"))
+        orders.append(k)
+    own = [p.beamform(d, k).cpu().numpy() for p, d, k in zip(plans, devs, orders)]
+    bt = hd.Batch(max_frames=len(plans), max_units=sum(p.info().n_tiles for p in plans),
+                  max_lds_bytes=max(p.info().lds_bytes for p in plans))
+    bt.set(plans, devs, orders, outs)
+    bt.launch()
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), own[i]), "frame %d differs from its own launch" % i
+    bt.capture()
+    for rep in range(2):
+        for o in outs:
+            o.fill_(float("nan"))
+        bt.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.array_equal(o.cpu().numpy(), own[i]), "replay %d frame %d" % (rep, i)
+    for i, ((f, arr, scale, grid), (_, _, _, flags, k)) in enumerate(zip(data, specs)):
+        o = O.beamform(arr, f.geometry, grid, k, dequant_scale=scale if dtype == "i16" else None,
+                       weighting="cf" if flags & hd.FLAG_CF else None)
+        err = rel_l2(own[i].astype(np.float64), o)
+        say("CF batch %s frame %d flags %d k=%d rel L2 %.2e" % (dtype, i, flags, k, err))
+        assert err <= TOL[dtype]
+    bt.close()
+    for p in plans:
+        p.close()

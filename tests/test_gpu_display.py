@@ -113,3 +113,32 @@ def test_display_abi_errors(hd):
     with pytest.raises(ValueError):
         disp.run(torch.zeros((64, 9), dtype=torch.float32, device="cuda"))
     disp.close()
+
+
+def test_display_batch_equals_single_runs(hd):
+    """hodmas_display_run_batch over 21 images (two full launch pairs of 16 and
+    a remainder of 5), some with envelope outputs and some without: each image
+    equals its own hodmas_display_run bit for bit, and its own maximum sets its
+    dB scale (images of very different amplitudes in one launch)."""
+    nz, nx, dz = 256, 40, 0.075e-3
+    rng = np.random.default_rng(5)
+    disp = hd.Display(nx, nz, dz, 1540.0, 2e6, 8e6, 31, 50.0)
+    imgs = [torch.from_numpy((rng.standard_normal((nz, nx)) * 10.0 ** (i % 5)).astype(np.float32)).cuda()
+            for i in range(21)]
+    envs = [torch.full_like(imgs[0], float("nan")) if i % 3 else None for i in range(21)]
+    envs_b, dbs_b = disp.run_batch(imgs, envs)
+    torch.cuda.synchronize()
+    for i, im in enumerate(imgs):
+        env1 = torch.empty_like(im)
+        _, db1 = disp.run(im, env1)
+        torch.cuda.synchronize()
+        assert torch.equal(db1, dbs_b[i]), "image %d dB" % i
+        if envs[i] is not None:
+            assert torch.equal(env1, envs_b[i]), "image %d envelope" % i
+    _, db_only = disp.run_batch(imgs[:3])
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert torch.equal(db_only[i], dbs_b[i])
+    with pytest.raises(ValueError):
+        disp.run_batch([])
+    disp.close()
