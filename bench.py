@@ -372,6 +372,9 @@ def bench_plain(args, torch):
         measured = {"fp32_add_tlane_s": round(r_v, 2), "fp32_fma_tlane_s": round(pk["fp32_fma"], 2),
                     "fp32_fma_sgpr_tlane_s": round(pk["fp32_fma_sgpr"], 2),
                     "trans_tlane_s": {n: round(pk[n], 2) for n in ("exp2", "log2", "sqrt", "rcp")},
+                    "bitwise_bfi_tlane_s": round(pk["int_bfi"], 2), "fract_tlane_s": round(pk["fract"], 2),
+                    "inner_loop_cycles_per_wave_element": {"constants_in_sgprs": round(pk["loop_cycles_sgpr"], 1),
+                                                           "constants_in_vgprs": round(pk["loop_cycles_vgpr"], 1)},
                     "hbm_copy_tb_s": round(pk["hbm_copy_tb_s"], 3),
                     "ceiling_gpixch_s": {str(k): round(v, 1) for k, v in ceil.items()},
                     "frac_of_ceiling": {str(k): round(got[k] / ceil[k], 4) for k in orders},
@@ -566,12 +569,17 @@ def bench_small(args, torch):
                "back_to_back_us_per_frame": round(b2b_ms * 1e3 / n_frames, 3),
                "back_to_back_gpixch_s": round(pixch * n_frames / (b2b_ms * 1e-3) / 1e9, 2)}
         # the same frames as one persistent launch, with the tiling the
-        # autotuner picks for batches (timed as a batch runs them)
-        for name, flags in (("batched", 0), ("batched_mirror_pairs", hodmas.FLAG_MIRROR)):
+        # autotuner picks for batches (timed as a batch runs them), and with
+        # the plan's default tiling (made for a single frame) for comparison
+        for name, flags in (("batched", 0), ("batched_mirror_pairs", hodmas.FLAG_MIRROR),
+                            ("batched_default_tiling", 0)):
             if flags and args.no_mirror:
                 continue
-            t = hodmas.autotune(geom, grid, S, "f32", k, flags=hodmas.FLAG_TUNE_BATCH | flags,
-                                cache_path=args.tune_cache)
+            if name == "batched_default_tiling":
+                t = None
+            else:
+                t = hodmas.autotune(geom, grid, S, "f32", k, flags=hodmas.FLAG_TUNE_BATCH | flags,
+                                    cache_path=args.tune_cache)
             q = hodmas.Plan(geom, grid, S, "f32", max_order=k, tiling=t, flags=flags)
             direct_ms, replay_ms = time_batch(q, k)
             qt = q.info().tiling

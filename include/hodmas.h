@@ -452,6 +452,16 @@ typedef struct {
     double exp2, log2, sqrt, rcp;   /* the transcendental unit */
     double hbm_copy_tb_s;   /* 1 GiB device-to-device copy: bytes read + written, 1e12/s */
     int32_t compute_units;
+    double int_bfi;         /* v_bfi_b32, all operands in VGPRs: the integer / bitwise class */
+    double fract;           /* v_fract_f32 */
+    /* The beamformer's inner loop as an instruction mix (per element: the
+     * delay, sample index and fraction, interpolation, signed sixth root,
+     * powers and six power-sum adds -- 27 VALU instructions, 4 of them
+     * transcendental; four independent elements per iteration; seven waves
+     * per SIMD): SIMD cycles per wave and element at 2.4 GHz, with the
+     * per-element constants wave-uniform in SGPRs (as the kernel holds them)
+     * and with them in VGPRs. */
+    double loop_cycles_sgpr, loop_cycles_vgpr;
 } hodmas_peaks;
 
 /* Run the probes on the current device, on `stream`, and wait for them (about

@@ -95,6 +95,13 @@ void release(hodmas_batch_s* b)
 
 bool valid_batch(const hodmas_batch_s* b) { return b && b->magic == kBatchMagic; }
 
+// Persistent workgroups a kind's kernel launches with: as many as its LDS lets
+// the device hold, cut to its unit count.
+int launch_grid(const hodmas_batch_s* b, int kind)
+{
+    return (int)std::min<int64_t>(b->kind_grid[kind], b->end[kind] - b->begin[kind]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -242,10 +249,49 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
         }
         kg[kind] = b->occ_per_cu[kind] * b->cus;
     }
-    // grouped by kind (one persistent kernel each), heaviest units first within a kind
-    std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) {
-        return x.kind != y.kind ? x.kind < y.kind : x.cost > y.cost;
-    });
+    // grouped by kind (one persistent kernel each), in frame and tile order
+    std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) { return x.kind < y.kind; });
+    int32_t kb[hodmas::kBatchKinds] = {}, ke[hodmas::kBatchKinds] = {};
+    for (size_t u = 0; u < units.size(); ++u) {
+        const int k = units[u].kind;
+        if (u == 0 || units[u - 1].kind != k)
+            kb[k] = (int32_t)u;
+        ke[k] = (int32_t)u + 1;
+    }
+    // Each kind's units, in frame and tile order (tile rows are depth bands),
+    // are cut into one contiguous run per XCD that has workgroups, of about
+    // equal estimated cost: an XCD then stages the RF of one frame, or of a
+    // band of depths, and reads that frame's tables, instead of every XCD
+    // fetching every frame.  Within a run the heaviest units go first.
+    int32_t cuts[hodmas::kBatchKinds][hodmas::kXcds + 1] = {};
+    try {
+        std::vector<int64_t> pre;
+        for (int k = 0; k < hodmas::kBatchKinds; ++k) {
+            const int n = ke[k] - kb[k];
+            if (n <= 0)
+                continue;
+            const int used = std::min<int>(hodmas::kXcds, (int)std::min<int64_t>(kg[k], n));
+            Unit* run = units.data() + kb[k];
+            pre.assign((size_t)n + 1, 0);
+            for (int u = 0; u < n; ++u)
+                pre[u + 1] = pre[u] + run[u].cost;
+            int32_t* cut = cuts[k];
+            for (int x = 1; x < used; ++x) {
+                const int64_t target = pre[n] * x / used;
+                int i = (int)(std::lower_bound(pre.begin(), pre.end(), target) - pre.begin());
+                i = std::max(i, cut[x - 1] + 1);     // every XCD in use gets a unit
+                i = std::min(i, n - (used - x));
+                cut[x] = i;
+            }
+            for (int x = used; x <= hodmas::kXcds; ++x)
+                cut[x] = n;
+            for (int x = 0; x < used; ++x)
+                std::stable_sort(run + cut[x], run + cut[x + 1],
+                                 [](const Unit& a, const Unit& c) { return a.cost > c.cost; });
+        }
+    } catch (const std::bad_alloc&) {
+        return HODMAS_ENOMEM;
+    }
     // the pinned staging buffer may still feed the previous asynchronous copy
     if (b->copy_pending && hipEventSynchronize(b->copied) != hipSuccess)
         return HODMAS_EDEVICE;
@@ -256,14 +302,9 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
     std::memset(hdr, 0, sizeof(BatchHeader));
     hdr->n_units = (int32_t)units.size();
     hdr->n_frames = n_frames;
-    for (int k = 0; k < hodmas::kBatchKinds; ++k)
-        hdr->begin[k] = hdr->end[k] = 0;
-    for (size_t u = 0; u < units.size(); ++u) {
-        const int k = units[u].kind;
-        if (u == 0 || units[u - 1].kind != k)
-            hdr->begin[k] = (int32_t)u;
-        hdr->end[k] = (int32_t)u + 1;
-    }
+    std::memcpy(hdr->begin, kb, sizeof(kb));
+    std::memcpy(hdr->end, ke, sizeof(ke));
+    std::memcpy(hdr->xcd, cuts, sizeof(cuts));
     std::memcpy(b->begin, hdr->begin, sizeof(b->begin));
     std::memcpy(b->end, hdr->end, sizeof(b->end));
     std::memcpy(b->kind_lds, kl, sizeof(kl));
@@ -304,8 +345,8 @@ hodmas_status hodmas_batch_launch(hodmas_batch_t b, void* stream)
     for (int kind = 0; kind < hodmas::kBatchKinds; ++kind) {
         if (b->end[kind] <= b->begin[kind])
             continue;
-        const int grid = (int)std::min<int64_t>(b->kind_grid[kind], b->end[kind] - b->begin[kind]);
-        if (hodmas::launch_batch(kind, hdr, frames, units, grid, comp, b->kind_lds[kind], stream) != 0) {
+        if (hodmas::launch_batch(kind, hdr, frames, units, launch_grid(b, kind), comp, b->kind_lds[kind], stream) !=
+            0) {
             (void)hipGetLastError();
             return HODMAS_EDEVICE;
         }
@@ -418,7 +459,7 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
         const int n = b->end[kind] - b->begin[kind];
         missing = missing || (n > 0 && !b->node[kind]);
         change = change || (n > 0) != b->node_on[kind] ||
-                 (n > 0 && ((int)std::min<int64_t>(b->kind_grid[kind], n) != b->node_grid[kind] ||
+                 (n > 0 && (launch_grid(b, kind) != b->node_grid[kind] ||
                             b->kind_lds[kind] != b->node_lds[kind]));
     }
     if ((change || missing) && b->replay_pending) {
@@ -443,7 +484,7 @@ hodmas_status hodmas_batch_replay(hodmas_batch_t b, void* stream)
         const int n = b->end[kind] - b->begin[kind];
         const bool on = n > 0;
         if (on) {
-            const int grid = (int)std::min<int64_t>(b->kind_grid[kind], n);
+            const int grid = launch_grid(b, kind);
             if (grid != b->node_grid[kind] || b->kind_lds[kind] != b->node_lds[kind]) {
                 const hipKernelNodeParams kp = node_params(b, kind, grid, b->kind_lds[kind], args);
                 if (hipGraphExecKernelNodeSetParams(b->exec, b->node[kind], &kp) != hipSuccess) {

@@ -84,6 +84,12 @@ hodmas_status validate(const hodmas_geometry* g, const hodmas_grid* gr, const ho
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// LDS of one staged chunk: `chunk` rows (twice that with pairing) of the
+// window and two more floats (after the first row's window: a pair of zeros,
+// the target of delays outside the record).
+int64_t row_stride(int64_t window) { return window + 2; }
+int64_t staged_bytes(int64_t chunk, int64_t window, int rows) { return chunk * row_stride(window) * 4 * rows; }
+
 // Mirror pairing needs whole tile columns, an even number of them.
 bool mirror_columns(int32_t nx, int32_t tile_x) { return nx % tile_x == 0 && (nx / tile_x) % 2 == 0; }
 
@@ -215,7 +221,7 @@ hodmas_status build_tables(hodmas_plan_s* p)
             td.check = check ? 1 : 0;
             td.first_entry = (int32_t)p->entries.size();
             max_window = std::max(max_window, window);
-            // slots in element order; the LDS window of slot s sits at (s % chunk) * window
+            // slots in element order; the LDS row of slot s starts at float (s % chunk) * (window + 2)
             std::vector<int> slot_elem;
             for (int i = 0; i < n; ++i)
                 if (act[i])
@@ -238,7 +244,7 @@ hodmas_status build_tables(hodmas_plan_s* p)
                         e.frac0 = fr[i];
                         e.lo = (float)(-(double)T0[i]);
                         e.hi = (float)((double)(S - 1) - (double)T0[i]);
-                        e.off = 4 * (T0[i] - wlo[i] + (sl % chunk) * window);
+                        e.off = (int32_t)(4 * (T0[i] - wlo[i] + (sl % chunk) * row_stride(window)));
                         e.channel = i;
                         p->entries.push_back(e);
                     }
@@ -333,7 +339,9 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         delete p;
         return st;
     }
-    // LDS: `chunk` windows of `max_window` floats; shrink the chunk until it fits.
+    // LDS: `chunk` windows of `max_window` floats and a pair of zeros (the
+    // target of delays outside the record), per row set; shrink the chunk
+    // until it fits.
     const int64_t block = int64_t(p->tiling.tile_x) * p->tiling.tile_z * p->tiling.split;
     // split-group combination: (sum, compensation) of up to MAX_ORDER power
     // sums plus the two coherence-factor sums per pixel, for each of `rows`
@@ -342,12 +350,12 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
                                  ((HODMAS_MAX_ORDER + 2) * 2 * rows + 1) * 4;
     // 40 KB keeps four workgroups on a CU (160 KB); an explicit chunk may use 64 KB
     const int64_t cap = auto_chunk ? 40 * 1024 : 64 * 1024;
-    if (int64_t(p->max_window) * 4 * rows > hodmas::kMaxLdsBytes) {
+    if (staged_bytes(1, p->max_window, rows) > hodmas::kMaxLdsBytes) {
         delete p;
         return HODMAS_EUNSUPPORTED;
     }
-    if (int64_t(p->tiling.chunk) * p->max_window * 4 * rows > cap) {
-        const int c = (int)std::max<int64_t>(1, cap / (int64_t(p->max_window) * 4 * rows));
+    if (staged_bytes(p->tiling.chunk, p->max_window, rows) > cap) {
+        const int c = (int)std::max<int64_t>(1, cap / (row_stride(p->max_window) * 4 * rows));
         // as many chunks as the cap needs, of equal size: no short last chunk
         // pays a full staging round, and the smaller LDS footprint can keep
         // more workgroups on a CU
@@ -359,7 +367,7 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
             return st;
         }
     }
-    p->lds_bytes = std::max<int64_t>(int64_t(p->tiling.chunk) * p->max_window * 4 * rows, reduce_bytes);
+    p->lds_bytes = std::max<int64_t>(staged_bytes(p->tiling.chunk, p->max_window, rows), reduce_bytes);
     const double fm = rf->frame_max > 0.f ? (double)rf->frame_max : 1.0;
     const double dq = rf->dtype == HODMAS_I16 ? (double)rf->dequant_scale : 1.0;
     p->in_scale = (float)(dq / fm);
@@ -450,7 +458,7 @@ hodmas_status hodmas_beamform_orders(hodmas_plan_t plan, const void* rf_dev, int
     const int64_t nt = hodmas::kOrderSums;
     const int64_t block = int64_t(plan->tiling.tile_x) * plan->tiling.tile_z * plan->tiling.split;
     const int64_t reduce = block / plan->tiling.split * (plan->tiling.split - 1) * (2 * nt + 1) * 4;
-    const int64_t lds = std::max<int64_t>(int64_t(plan->tiling.chunk) * plan->max_window * 4, reduce);
+    const int64_t lds = std::max<int64_t>(staged_bytes(plan->tiling.chunk, plan->max_window, 1), reduce);
     if (lds > 64 * 1024)
         return HODMAS_EUNSUPPORTED;
     int cur = -1;

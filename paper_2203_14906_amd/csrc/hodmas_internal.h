@@ -58,11 +58,15 @@ static_assert(batch_kind(kind_order(kBatchKinds - 1), kind_dtype(kBatchKinds - 1
 
 constexpr int kXcds = 8;                    // workgroup b runs on XCD b mod 8
 
+// xcd[k][x] .. xcd[k][x+1]: the units of kind k (relative to begin[k]) that
+// the workgroups on XCD x walk -- a run of neighbouring tiles of one or a few
+// frames, so the RF and tables they read stay in that XCD's L2.
 struct BatchHeader {
     int32_t n_units;
     int32_t n_frames;
     int32_t begin[kBatchKinds];
     int32_t end[kBatchKinds];
+    int32_t xcd[kBatchKinds][kXcds + 1];
 };
 
 struct BatchFrame {

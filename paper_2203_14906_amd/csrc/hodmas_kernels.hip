@@ -113,20 +113,24 @@ __device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, floa
     return p;
 }
 
+// Tiles whose delays may leave the record (CHECK): a delay outside [lo, hi]
+// -- before the first sample or past the last -- contributes nothing, so its
+// address is pointed at a pair of zeros the staging keeps after the rows
+// (`zero`, bytes) and the interpolation yields exactly 0.
+__device__ __forceinline__ void redirect(Tap& p, const hodmas_chan_entry& e, int zero)
+{
+    p.addr = (p.t >= e.lo && p.t <= e.hi) ? p.addr : zero;
+}
+
 __device__ __forceinline__ float lds_at(const float* __restrict__ lds, int addr)
 {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + addr);
 }
 
-// Linear interpolation between the two staged samples; outside [0, S-1] the
-// element contributes nothing (only tested in tiles that reach the record ends).
-template <bool CHECK>
-__device__ __forceinline__ float interp(const Tap& p, const hodmas_chan_entry& e, float s0, float s1)
+// Linear interpolation between the two staged samples.
+__device__ __forceinline__ float interp(const Tap& p, float s0, float s1)
 {
-    float v = __builtin_fmaf(p.f, s1 - s0, s0);
-    if (CHECK)
-        v = (p.t >= e.lo && p.t <= e.hi) ? v : 0.f;
-    return v;
+    return __builtin_fmaf(p.f, s1 - s0, s0);
 }
 
 // y^1 .. y^K of the signed K-th root of v.
@@ -187,10 +191,17 @@ __device__ __forceinline__ void terms(float v, float (&T)[n_sums<K, CF>()])
     }
 }
 
-// Rows [0, nch) of the LDS receive the chunk's slots (row r: slot r's element
-// over its sample window).  With M == 2 (mirror pairing) rows [nch, 2 nch)
-// receive the mirrored elements, n_elements - 1 - element, over the same
-// sample windows: the mirror pixel reads them at the same delays.
+// LDS layout of a staged chunk: rows of window + 2 floats.  Rows [0, nch) hold
+// the chunk's slots (row r: slot r's element over its sample window), and the
+// two floats after row 0's window are zeros, the target of out-of-record
+// delays.  With M == 2 (mirror pairing) rows [nch, 2 nch) hold the mirrored
+// elements, n_elements - 1 - element, over the same sample windows: the mirror
+// pixel reads them at the same delays, mirror_offset bytes on -- which also
+// takes the zeros' address to the same two floats of row nch.
+__device__ __forceinline__ int row_stride(int window) { return window + 2; }
+__device__ __forceinline__ int zero_offset(int window) { return window * 4; }
+__device__ __forceinline__ int mirror_offset(int nch, int window) { return nch * row_stride(window) * 4; }
+
 template <int DT, int M>
 __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, int nch, int window,
                                             float* __restrict__ lds, int wave, int nwaves, int lane)
@@ -214,6 +225,9 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
     const char* rf = static_cast<const char*>(A.rf);
     const int64_t row_bytes = int64_t(A.stride) * esz;
     const int record_bytes = A.n_samples * esz;
+    const int stride = row_stride(window);
+    if (wave == 0 && lane < 2 * M)
+        lds[(lane >> 1) * nch * stride + window + (lane & 1)] = 0.f;
     for (int c = s0; c < s1; c += 64) {
         const int j = min(c + lane, s1 - 1);
         const bool mirrored = M == 2 && j >= nch;
@@ -241,9 +255,11 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
                         v[m] = (float)(short)__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
                 }
 #pragma unroll
-                for (int m = 0; m < kInFlight; ++m)
+                for (int m = 0; m < kInFlight; ++m) {
+                    const int row = c + m0 + m;
                     if (m0 + m < cend && i < window)
-                        lds[(c + m0 + m) * window + i] = v[m] * A.in_scale;
+                        lds[row * stride + i] = v[m] * A.in_scale;
+                }
             }
         }
     }
@@ -287,10 +303,11 @@ __device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[
 // counter does not order scalar loads, so issuing them earlier would make
 // this group's waits also wait for them), then roots, powers and the sums.
 // With M == 2 each delay also serves the lane's mirror pixel, whose samples
-// sit `moff` bytes further on in the LDS (the mirrored rows).
+// sit `moff` bytes further on in the LDS (the mirrored rows).  `zero`: the
+// LDS byte address of the zero pair (CHECK).
 template <int K, bool CF, bool COMP, bool CHECK, int M, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], float u2, float q,
-                                              const float* __restrict__ lds, int moff, float (&s)[M][NS],
+                                              const float* __restrict__ lds, int moff, int zero, float (&s)[M][NS],
                                               float (&P)[M][NS], bool more, ConstEntry En,
                                               hodmas_chan_entry (&en)[4])
 {
@@ -299,6 +316,11 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         tp[m] = locate(e[m], u2, q);
+    if (CHECK) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            redirect(tp[m], e[m], zero);
+    }
 #pragma unroll
     for (int mm = 0; mm < M; ++mm) {
 #pragma unroll
@@ -311,7 +333,7 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
     for (int mm = 0; mm < M; ++mm) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            v[mm][m] = interp<CHECK>(tp[m], e[m], s0[mm][m], s1[mm][m]);
+            v[mm][m] = interp(tp[m], s0[mm][m], s1[mm][m]);
     }
     // emits nothing: makes the samples (hence this group's LDS waits)
     // complete before the scalar loads below are issued
@@ -356,7 +378,7 @@ __device__ __forceinline__ void after_group(int& groups, float (&s)[M][NS], floa
 // so nothing is copied between them.
 template <int K, bool CF, bool COMP, bool CHECK, int M, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, float q,
-                                                 const float* __restrict__ lds, int moff, float (&s)[M][NS],
+                                                 const float* __restrict__ lds, int moff, int zero, float (&s)[M][NS],
                                                  float (&c)[M][NS])
 {
     float P[M][NS];
@@ -373,13 +395,13 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK, M>(ea, u2, q, lds, moff, s, P, more_a, E + sl + 4, eb);
+            process_group<K, CF, COMP, CHECK, M>(ea, u2, q, lds, moff, zero, s, P, more_a, E + sl + 4, eb);
             after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK, M>(eb, u2, q, lds, moff, s, P, more_b, E + sl + 4, ea);
+            process_group<K, CF, COMP, CHECK, M>(eb, u2, q, lds, moff, zero, s, P, more_b, E + sl + 4, ea);
             after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_b)
@@ -388,12 +410,14 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
     }
     for (; sl < n; ++sl) {
         const hodmas_chan_entry e = load_const(E, sl);
-        const Tap tp = locate(e, u2, q);
+        Tap tp = locate(e, u2, q);
+        if (CHECK)
+            redirect(tp, e, zero);
 #pragma unroll
         for (int mm = 0; mm < M; ++mm) {
             float T[NS];
             const int addr = tp.addr + mm * moff;
-            terms<K, CF>(interp<CHECK>(tp, e, lds_at(lds, addr), lds_at(lds, addr + 4)), T);
+            terms<K, CF>(interp(tp, lds_at(lds, addr), lds_at(lds, addr + 4)), T);
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
                 if (COMP)
@@ -437,11 +461,11 @@ __device__ __forceinline__ R newton(const R (&p)[K])
 // symmetric about x = 0 (checked on the host), that pixel's delay to element
 // n-1-i equals this pixel's delay to element i, so one delay serves both and
 // the mirror pixel gathers from the mirrored rows the staging fills.
-template <int K, int DT, bool COMP, bool CF = false, int M = 1>
-__device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
+template <int K, int DT, bool COMP, bool CF, int M, bool CHECK>
+__device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_tile_desc& td,
+                                             float* __restrict__ lds)
 {
     constexpr int NS = n_sums<K, CF>();
-    const hodmas_tile_desc td = load_const(A.tiles, tile);
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
     const int nwaves = A.block >> 6;
@@ -453,17 +477,18 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
     const bool valid = lx < td.nx && lz < td.nz;
     const int ix = td.ix0 + min(lx, td.nx - 1);
     const int iz = td.iz0 + min(lz, td.nz - 1);
-    Global<float> dst[M];
-    dst[0] = global_ptr(A.image + (int64_t)iz * A.nx + ix);
-    if constexpr (M == 2)
-        dst[1] = global_ptr(A.image + (int64_t)iz * A.nx + (A.nx - 1 - ix));
+    // the lane's pixel (mm = 0) and, with M == 2, its mirror image; formed
+    // where it is stored, so no 64-bit address stays live through the loops
+    auto dst = [&](int mm) {
+        return global_ptr(A.image + (int64_t)iz * A.nx + (mm == 0 ? ix : A.nx - 1 - ix));
+    };
 
     if (td.n_active < K) {
         // fewer contributing elements than the order: no K-subset exists, e_K = 0 exactly
         if (g == 0 && valid) {
 #pragma unroll
             for (int mm = 0; mm < M; ++mm)
-                *dst[mm] = 0.f;
+                *dst(mm) = 0.f;
         }
         return;
     }
@@ -490,16 +515,14 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
         __syncthreads();                       // previous readers of the LDS are done
         stage_chunk<DT, M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
-        const int moff = nch * td.window * 4;  // bytes from a slot's row to its mirrored row
+        const int moff = mirror_offset(nch, td.window);  // bytes from a slot's row to its mirrored row
+        const int zero = zero_offset(td.window);
         // this group's elements of the chunk: slots g, g+split, ..., stored together
         int goff = 0;
         for (int h = 0; h < g; ++h)
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
-        if (td.check)
-            accumulate_chunk<K, CF, COMP, true, M>(E + c0 + goff, ng, u2, q, lds, moff, s, c);
-        else
-            accumulate_chunk<K, CF, COMP, false, M>(E + c0 + goff, ng, u2, q, lds, moff, s, c);
+        accumulate_chunk<K, CF, COMP, CHECK, M>(E + c0 + goff, ng, u2, q, lds, moff, zero, s, c);
     }
 
     if (A.split > 1) {
@@ -554,11 +577,26 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, int tile, float
             const double s1 = COMP ? double(s[mm][K]) - double(c[mm][K]) : double(s[mm][K]);
             const double s2 = COMP ? double(s[mm][K + 1]) - double(c[mm][K + 1]) : double(s[mm][K + 1]);
             const double cf = s2 > 0.0 ? (s1 * s1) / (double(A.n_elements) * s2) : 0.0;
-            *dst[mm] = (float)(double(ek) * cf * double(A.out_scale));
+            *dst(mm) = (float)(double(ek) * cf * double(A.out_scale));
         } else {
-            *dst[mm] = (float)(ek * R(A.out_scale));
+            *dst(mm) = (float)(ek * R(A.out_scale));
         }
     }
+}
+
+// Tiles that reach the record ends take the body with the range test, the
+// others the body without it.  The choice is made once per tile, so each body
+// is a whole of its own: with the test inside the element loop, or with both
+// loop variants in one body, the paired kernels' sums no longer fit their
+// registers and the loop's scheduling suffers.
+template <int K, int DT, bool COMP, bool CF = false, int M = 1>
+__device__ __forceinline__ void form_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
+{
+    const hodmas_tile_desc td = load_const(A.tiles, tile);
+    if (td.check)
+        process_tile<K, DT, COMP, CF, M, true>(A, td, lds);
+    else
+        process_tile<K, DT, COMP, CF, M, false>(A, td, lds);
 }
 
 // M == 1: workgroup b forms tile xcd_tile(b).  M == 2: workgroup b forms pair
@@ -569,27 +607,30 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 {
     extern __shared__ float lds[];
     if constexpr (M == 1) {
-        process_tile<K, DT, COMP, CF, 1>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
+        form_tile<K, DT, COMP, CF, 1>(A, xcd_tile(blockIdx.x, A.n_tiles), lds);
     } else {
         const int half = A.nx / A.tile_x / 2;     // tile columns left of the centre
         const int p = xcd_tile(blockIdx.x, A.n_tiles / 2);
         const int bz = p / half;
-        process_tile<K, DT, COMP, CF, 2>(A, bz * 2 * half + (p - bz * half), lds);
+        form_tile<K, DT, COMP, CF, 2>(A, bz * 2 * half + (p - bz * half), lds);
     }
 }
 
 // Persistent form: one kernel per (order, storage type, pairing, coherence
-// weighting).  Its fixed
-// grid walks that kind's slice of the batch's work list -- (frame, tile) units
-// of many frames with their own plans, sorted by estimated cost -- with
-// workgroup b taking units b, 2G-1-b, 2G+b, ... (a snake, which evens out the
-// per-workgroup cost).  With M == 2 a unit is a mirror pair, named by its left
-// tile.  Each unit runs exactly the code of the per-frame kernel, so a frame's
-// image does not depend on what else is in the batch.
-// Mirror pairs keep two pixels' sums per lane; from order 4 on that would take
-// a paired kernel above 80 VGPRs (4-5 waves per SIMD), while a 64-element
-// chunk's LDS leaves room for six workgroups per CU.  Asking for six waves
-// costs a few spills per staged chunk, none in the element loop.
+// weighting).  Its fixed grid walks that kind's slice of the batch's work
+// list -- (frame, tile) units of many frames with their own plans.  The slice
+// is cut into one run per XCD (neighbouring tiles of one or a few frames, of
+// about equal estimated cost, each sorted by cost); the g workgroups on XCD x
+// (workgroups x, x+8, ...) walk run x, the l-th of them taking units l,
+// 2g-1-l, 2g+l, ... (a snake, which evens out the per-workgroup cost).  With
+// M == 2 a unit is a mirror pair, named by its left tile.  Each unit runs
+// exactly the code of the per-frame kernel, so a frame's image does not depend
+// on what else is in the batch.
+// Mirror pairs keep two pixels' sums per lane.  At order 6 that takes a paired
+// kernel a little above 80 VGPRs (five waves per SIMD), while a 64-element
+// chunk's LDS leaves room for six workgroups per CU; asking for six waves
+// costs a few dwords of spill per tile (values kept for the final store), none
+// in the loops.  Orders 4 and 5 fit in seven waves without asking.
 constexpr int batch_min_waves(int K, int M) { return M == 2 && K >= 4 ? 6 : 1; }
 
 template <int K, int DT, bool COMP, bool CF, int M>
@@ -599,17 +640,18 @@ void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr, const BatchFrame* 
 {
     extern __shared__ float lds[];
     constexpr int kind = batch_kind(K, DT, M, CF ? 1 : 0);
-    const BatchHeader h = load_const(hdr, 0);
-    const int first = h.begin[kind];
-    const int n = h.end[kind] - first;
-    const int G = gridDim.x;
-    for (int r = 0; r * G < n; ++r) {
-        const int u = (r & 1) ? (r + 1) * G - 1 - (int)blockIdx.x : r * G + (int)blockIdx.x;
+    const int x = (int)blockIdx.x % kXcds, l = (int)blockIdx.x / kXcds;
+    const int g = ((int)gridDim.x - x + kXcds - 1) / kXcds;   // workgroups on this XCD
+    const int lo = load_const(&hdr->xcd[kind][0], x);
+    const int first = load_const(&hdr->begin[0], kind) + lo;
+    const int n = load_const(&hdr->xcd[kind][0], x + 1) - lo;
+    for (int r = 0; r * g < n; ++r) {
+        const int u = (r & 1) ? (r + 1) * g - 1 - l : r * g + l;
         if (u >= n)
             continue;
         const BatchUnit un = load_const(units, first + u);
         const BatchFrame fr = load_const(frames, un.frame);
-        process_tile<K, DT, COMP, CF, M>(fr.args, un.tile, lds);
+        form_tile<K, DT, COMP, CF, M>(fr.args, un.tile, lds);
     }
 }
 
@@ -696,7 +738,7 @@ __device__ __forceinline__ void terms_all(float v, float (&T)[kSums])
 
 template <int KMAX, bool COMP, bool CHECK>
 __device__ __forceinline__ void process_group_all(const hodmas_chan_entry (&e)[4], float u2, float q,
-                                                  const float* __restrict__ lds, float (&s)[kSums],
+                                                  const float* __restrict__ lds, int zero, float (&s)[kSums],
                                                   float (&P)[kSums], bool more, ConstEntry En,
                                                   hodmas_chan_entry (&en)[4])
 {
@@ -705,6 +747,11 @@ __device__ __forceinline__ void process_group_all(const hodmas_chan_entry (&e)[4
 #pragma unroll
     for (int m = 0; m < 4; ++m)
         tp[m] = locate(e[m], u2, q);
+    if (CHECK) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            redirect(tp[m], e[m], zero);
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         s0[m] = lds_at(lds, tp[m].addr);
@@ -712,7 +759,7 @@ __device__ __forceinline__ void process_group_all(const hodmas_chan_entry (&e)[4
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        v[m] = interp<CHECK>(tp[m], e[m], s0[m], s1[m]);
+        v[m] = interp(tp[m], s0[m], s1[m]);
     asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]) : "memory");
     if (more)
         load_group(En, en);
@@ -750,7 +797,7 @@ __device__ __forceinline__ void flush_all(float (&s)[kSums], float (&c)[kSums], 
 
 template <int KMAX, bool COMP, bool CHECK>
 __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float u2, float q,
-                                                     const float* __restrict__ lds, float (&s)[kSums],
+                                                     const float* __restrict__ lds, int zero, float (&s)[kSums],
                                                      float (&c)[kSums])
 {
     float P[kSums];
@@ -764,14 +811,14 @@ __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float 
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group_all<KMAX, COMP, CHECK>(ea, u2, q, lds, s, P, more_a, E + sl + 4, eb);
+            process_group_all<KMAX, COMP, CHECK>(ea, u2, q, lds, zero, s, P, more_a, E + sl + 4, eb);
             if (COMP && (++groups & 7) == 0)
                 flush_all<KMAX, COMP>(s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group_all<KMAX, COMP, CHECK>(eb, u2, q, lds, s, P, more_b, E + sl + 4, ea);
+            process_group_all<KMAX, COMP, CHECK>(eb, u2, q, lds, zero, s, P, more_b, E + sl + 4, ea);
             if (COMP && (++groups & 7) == 0)
                 flush_all<KMAX, COMP>(s, c, P);
             sl += 4;
@@ -781,9 +828,11 @@ __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float 
     }
     for (; sl < n; ++sl) {
         const hodmas_chan_entry e = load_const(E, sl);
-        const Tap tp = locate(e, u2, q);
+        Tap tp = locate(e, u2, q);
+        if (CHECK)
+            redirect(tp, e, zero);
         float T[kSums];
-        terms_all<KMAX>(interp<CHECK>(tp, e, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
+        terms_all<KMAX>(interp(tp, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
 #pragma unroll
         for (int j = 0; j < kSums; ++j) {
             if (!sum_needed(j, KMAX))
@@ -810,12 +859,11 @@ __device__ __forceinline__ void store_order(const float (&s)[kSums], const float
     *dst = (float)(newton<K, R>(p) * R(out_scale));
 }
 
-template <int KMAX, int DT, bool COMP>
-__global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, OrderImages out)
+template <int KMAX, int DT, bool COMP, bool CHECK>
+__device__ __forceinline__ void orders_tile(const FrameArgs& A, const OrderImages& out, const hodmas_tile_desc& td,
+                                            float* __restrict__ lds)
 {
-    extern __shared__ float lds[];
     constexpr int NT = kSums;
-    const hodmas_tile_desc td = load_const(A.tiles, xcd_tile(blockIdx.x, A.n_tiles));
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
     const int nwaves = A.block >> 6;
@@ -852,10 +900,7 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
         for (int h = 0; h < g; ++h)
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
-        if (td.check)
-            accumulate_chunk_all<KMAX, COMP, true>(E + c0 + goff, ng, u2, q, lds, s, c);
-        else
-            accumulate_chunk_all<KMAX, COMP, false>(E + c0 + goff, ng, u2, q, lds, s, c);
+        accumulate_chunk_all<KMAX, COMP, CHECK>(E + c0 + goff, ng, u2, q, lds, zero_offset(td.window), s, c);
     }
     if (A.split > 1) {
         __syncthreads();
@@ -898,6 +943,17 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, O
     if constexpr (KMAX >= 4) { if (na >= 4) store_order<4, COMP>(s, c, A.out_scale, out.img[3] + pix); else out.img[3][pix] = 0.f; }
     if constexpr (KMAX >= 5) { if (na >= 5) store_order<5, COMP>(s, c, A.out_scale, out.img[4] + pix); else out.img[4][pix] = 0.f; }
     if constexpr (KMAX >= 6) { if (na >= 6) store_order<6, COMP>(s, c, A.out_scale, out.img[5] + pix); else out.img[5][pix] = 0.f; }
+}
+
+template <int KMAX, int DT, bool COMP>
+__global__ __launch_bounds__(kMaxBlock) void hodmas_orders_kernel(FrameArgs A, OrderImages out)
+{
+    extern __shared__ float lds[];
+    const hodmas_tile_desc td = load_const(A.tiles, xcd_tile(blockIdx.x, A.n_tiles));
+    if (td.check)
+        orders_tile<KMAX, DT, COMP, true>(A, out, td, lds);
+    else
+        orders_tile<KMAX, DT, COMP, false>(A, out, td, lds);
 }
 
 template <int KMAX, int DT>

@@ -100,7 +100,9 @@ class Metrics(ctypes.Structure):
 class Peaks(ctypes.Structure):
     _fields_ = [("fp32_add", ctypes.c_double), ("fp32_fma", ctypes.c_double), ("fp32_fma_sgpr", ctypes.c_double),
                 ("exp2", ctypes.c_double), ("log2", ctypes.c_double), ("sqrt", ctypes.c_double),
-                ("rcp", ctypes.c_double), ("hbm_copy_tb_s", ctypes.c_double), ("compute_units", ctypes.c_int32)]
+                ("rcp", ctypes.c_double), ("hbm_copy_tb_s", ctypes.c_double), ("compute_units", ctypes.c_int32),
+                ("int_bfi", ctypes.c_double), ("fract", ctypes.c_double), ("loop_cycles_sgpr", ctypes.c_double),
+                ("loop_cycles_vgpr", ctypes.c_double)]
 
 
 class DisplayDesc(ctypes.Structure):

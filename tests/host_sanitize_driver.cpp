@@ -82,9 +82,10 @@ void check_tables(hodmas_plan_t p, const Case& c)
             const hodmas_chan_entry& e = ent[td.first_entry + s];
             EXPECT(e.channel >= 0 && e.channel < c.n);
             EXPECT(std::isfinite(e.a) && std::isfinite(e.d0sq) && e.d0 > 0.f && e.frac0 >= 0.f && e.frac0 <= 1.f);
-            // the entry's offset, in floats, lies in some slot's window row of the chunk
-            const int off = e.off / 4;
-            EXPECT(e.off % 4 == 0 && off >= 0 && off < chunk * td.window);
+            // the entry's offset, in floats, lies in the window part of some slot's
+            // row of the chunk (rows of window + 2 floats)
+            const int off = e.off / 4, stride = td.window + 2;
+            EXPECT(e.off % 4 == 0 && off >= 0 && off < chunk * stride && off % stride < td.window);
         }
     }
     for (int v : covered)

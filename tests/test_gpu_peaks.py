@@ -20,3 +20,8 @@ def test_measured_peaks_are_plausible():
     for t in ("exp2", "log2", "sqrt", "rcp"):
         assert p[t] < p["fp32_add"]
     assert 0.5 < p["hbm_copy_tb_s"] < 20.0
+    # the bitwise class issues no faster than FP32 adds; the inner-loop mix
+    # costs between one and ten cycles per instruction (27 per element)
+    assert 0.0 < p["int_bfi"] <= p["fp32_add"] * 1.05 and 0.0 < p["fract"] <= p["fp32_add"] * 1.05
+    for k in ("loop_cycles_sgpr", "loop_cycles_vgpr"):
+        assert 27.0 < p[k] < 270.0, k

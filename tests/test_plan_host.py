@@ -150,7 +150,7 @@ def test_tables_cover_every_delay(case):
             assert e.hi == pytest.approx(S - 1 - T0, abs=0)
             ta = math.sqrt((td.xa - ex[i] / LAM) ** 2 + td.za ** 2) - t0s
             assert T0 == math.floor(ta) and e.frac0 == pytest.approx(ta - T0, abs=1e-6)
-            assert e.off == 4 * (T0 - st.first_sample + (slot % chunk) * td.window)
+            assert e.off == 4 * (T0 - st.first_sample + (slot % chunk) * (td.window + 2))
             # float32 reconstruction of each pixel's delay, as the kernel forms it
             num = (u2.astype(np.float64) * np.float64(e.a) + q).astype(np.float32)
             d = np.sqrt(np.abs(np.float64(e.d0sq) + num)).astype(np.float32)
@@ -173,7 +173,9 @@ def test_default_tiling_and_info():
     assert (inf.tiling.tile_x, inf.tiling.tile_z, inf.tiling.split) == (16, 16, 1)
     assert inf.n_tiles == 32 * 32
     assert inf.active_pairs == 32 * 32 * 128           # no element is out of the record here
-    assert inf.lds_bytes == inf.tiling.chunk * inf.max_window * 4
+    # rows of the window and two floats more (the first row's hold the zeros
+    # that delays outside the record read)
+    assert inf.lds_bytes == inf.tiling.chunk * (inf.max_window + 2) * 4
     small = _plan(ph.config_frame(1).geometry, ph.config_frame(1).grid, 1024)
     assert small.info().tiling.split in (2, 4)
     p.close()
@@ -245,7 +247,7 @@ def test_mirror_lds_holds_both_rows():
     mir = _plan(f.geometry, f.grid, 2048, flags=hodmas.FLAG_MIRROR)
     a, b = plain.info(), mir.info()
     assert b.max_window == a.max_window
-    assert b.lds_bytes == 2 * b.tiling.chunk * b.max_window * 4 <= 40 * 1024
+    assert b.lds_bytes == 2 * b.tiling.chunk * (b.max_window + 2) * 4 <= 40 * 1024
     assert b.tiling.chunk <= a.tiling.chunk
     # the automatic chunk splits the 128 elements into equal chunks
     assert b.tiling.chunk == 64
@@ -266,10 +268,11 @@ def test_automatic_chunks_are_balanced():
             rows = 2 if flags else 1
             c, win = inf.tiling.chunk, inf.max_window
             n_chunks = -(-n // c)
-            assert inf.lds_bytes >= c * win * 4 * rows
-            assert c * win * 4 * rows <= 40 * 1024
+            staged = c * (win + 2) * 4 * rows
+            assert inf.lds_bytes >= staged
+            assert staged <= 40 * 1024
             assert n - (n_chunks - 1) * c >= c - n_chunks       # last chunk nearly full
-            largest = max(1, 40 * 1024 // (win * 4 * rows))
+            largest = max(1, 40 * 1024 // ((win + 2) * 4 * rows))
             assert n_chunks == -(-n // min(n, largest))         # no more chunks than the cap needs
             p.close()
 
