@@ -216,6 +216,11 @@ hodmas_status build_tables(hodmas_plan_s* p)
                 whi[i] = (int32_t)std::floor(tmax) + 2;
                 window = std::max(window, whi[i] - wlo[i] + 1);
             }
+            // every staged row -- `window` samples from the element's first --
+            // must lie inside the record for the untested path, which copies
+            // rows without bounds (FP32) and tests no delay
+            for (int i = 0; i < n && !check; ++i)
+                check = act[i] && (wlo[i] < 0 || int64_t(wlo[i]) + window > S);
             td.n_active = n_active;
             td.window = window;
             td.check = check ? 1 : 0;
@@ -368,7 +373,10 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         }
     }
     p->lds_bytes = std::max<int64_t>(staged_bytes(p->tiling.chunk, p->max_window, rows), reduce_bytes);
-    const double fm = rf->frame_max > 0.f ? (double)rf->frame_max : 1.0;
+    // FP16 / int16: widened samples are normalised by frame_max and the result
+    // scaled back; FP32 samples are used as stored, so the kernel may copy
+    // them into LDS untouched
+    const double fm = rf->frame_max > 0.f && rf->dtype != HODMAS_F32 ? (double)rf->frame_max : 1.0;
     const double dq = rf->dtype == HODMAS_I16 ? (double)rf->dequant_scale : 1.0;
     p->in_scale = (float)(dq / fm);
     p->out_scale = (float)fm;
@@ -409,6 +417,9 @@ FrameArgs hodmas::frame_args(const hodmas_plan_s* plan, const void* rf_dev, floa
     a.dzs = plan->dzs;
     a.in_scale = plan->in_scale;
     a.out_scale = plan->out_scale;
+    a.direct = plan->rf.dtype == HODMAS_F32 &&
+               int64_t(plan->geom.n_elements) * plan->rf.channel_stride * 4 < (int64_t(1) << 31);
+    a.pad = 0;
     return a;
 }
 

@@ -265,6 +265,51 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
     }
 }
 
+// FP32 tiles whose rows lie inside the record (the plan marks the others as
+// tested) copy each row from memory straight into LDS: buffer loads that write
+// LDS, one per 64 samples, through one buffer resource over the whole frame,
+// with the row's start in the scalar offset.  One vector pass forms 64 rows'
+// offsets (lane j: row j), so a row then costs one lane read, scalar work and
+// one load per wave -- no vector registers in flight, no conversion and no LDS
+// store, where the general staging above spends several vector instructions
+// per row.
+template <int M>
+__device__ __forceinline__ void stage_direct(const FrameArgs& A, ConstStage st, int nch, int window,
+                                             float* __restrict__ lds, int wave, int nwaves, int lane)
+{
+    using LdsPtr = __attribute__((address_space(3))) void*;
+    const int rows = M * nch;
+    const int per_wave = (rows + nwaves - 1) / nwaves;
+    const int s0 = wave * per_wave;
+    const int s1 = min(rows, s0 + per_wave);
+    const int stride = row_stride(window);
+    if (wave == 0 && lane < 2 * M)
+        lds[(lane >> 1) * nch * stride + window + (lane & 1)] = 0.f;
+    const int bytes = A.n_elements * (int)A.stride * 4;   // below 2^31 when A.direct is set
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.rf), (short)0, bytes, kBufferFlags);
+    const Global<const int> ent = global_ptr(reinterpret_cast<const int*>(st));
+    for (int c = s0; c < s1; c += 64) {
+        const int j = min(c + lane, s1 - 1);
+        const bool mirrored = M == 2 && j >= nch;
+        const int src = mirrored ? j - nch : j;
+        const int elem = ent[2 * src];
+        const int ch = mirrored ? A.n_elements - 1 - elem : elem;
+        const int my_off = (ch * (int)A.stride + ent[2 * src + 1]) * 4;
+        const int cend = __builtin_amdgcn_readfirstlane(min(s1 - c, 64));
+        for (int b = 0; b < window; b += 64) {
+            if (b + lane < window) {
+                for (int m = 0; m < cend; ++m) {
+                    const int soff = __builtin_amdgcn_readlane(my_off, m);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsPtr)(lds + (c + m) * stride + b), 4,
+                                                             (b + lane) * 4, soff, 0, 0);
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // the copies are in LDS before the caller's barrier
+}
+
 // Workgroups are dealt to the eight XCDs round-robin (workgroup b runs on XCD
 // b mod 8).  Give each XCD a contiguous run of tiles -- a band of tile rows --
 // so the RF samples an XCD stages come from a narrow range of delays and its
@@ -513,7 +558,10 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();                       // previous readers of the LDS are done
-        stage_chunk<DT, M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        if (DT == HODMAS_F32 && !CHECK && A.direct)
+            stage_direct<M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        else
+            stage_chunk<DT, M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
         const int moff = mirror_offset(nch, td.window);  // bytes from a slot's row to its mirrored row
         const int zero = zero_offset(td.window);
@@ -894,7 +942,10 @@ __device__ __forceinline__ void orders_tile(const FrameArgs& A, const OrderImage
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();
-        stage_chunk<DT, 1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        if (DT == HODMAS_F32 && !CHECK && A.direct)
+            stage_direct<1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        else
+            stage_chunk<DT, 1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
         int goff = 0;
         for (int h = 0; h < g; ++h)
