@@ -678,11 +678,13 @@ __global__ __launch_bounds__(kMaxBlock) void hodmas_frame_kernel(FrameArgs A)
 // kernel a little above 80 VGPRs (five waves per SIMD), while a 64-element
 // chunk's LDS leaves room for six workgroups per CU; asking for six waves
 // costs a few dwords of spill per tile (values kept for the final store), none
-// in the loops.  Orders 4 and 5 fit in seven waves without asking.
-constexpr int batch_min_waves(int K, int M) { return M == 2 && K >= 4 ? 6 : 1; }
+// in the loops.  Lower orders fit six or seven waves without asking; with
+// coherence weighting (two more sums per pixel) six waves would spill inside
+// the loops, so those kernels are left at the four or five they fit.
+constexpr int batch_min_waves(int K, int M, bool CF) { return M == 2 && K == 6 && !CF ? 6 : 1; }
 
 template <int K, int DT, bool COMP, bool CF, int M>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_min_waves(K, M))))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_min_waves(K, M, CF))))
 void hodmas_batch_kernel(const BatchHeader* __restrict__ hdr, const BatchFrame* __restrict__ frames,
                          const BatchUnit* __restrict__ units)
 {

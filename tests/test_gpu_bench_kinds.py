@@ -18,6 +18,9 @@ sum over element subsets of signed k-th roots of the delayed samples).
   the bar -- elsewhere the kernel adds no more than its own 2e-5 to it).
 - The reduced-precision workload (256 elements, 1024x1024, int16 and FP16)
   on full images at every order, unpaired and paired, against both oracles.
+- The FP32 staging the step uses (rows copied straight from memory into LDS)
+  against the register path with every delay tested (FLAG_FORCE_CHECK), on
+  the step's frame, paired and unpaired, per frame and batched: bit for bit.
 """
 import sys
 
@@ -226,3 +229,33 @@ def test_reduced_workload_full_images_both_oracles(hd, dtype):
             check_storage_bar(dtype, k, e_pre, store)
     for p in plans.values():
         p.close()
+
+
+def test_direct_rows_equal_register_staging(hd):
+    """Config 2 lies wholly inside its records, so every tile of the default
+    plans copies its FP32 rows straight into LDS; FLAG_FORCE_CHECK sends every
+    tile through the register staging and the per-delay range test instead.
+    Both stage the same stored values and test nothing that can fail here, so
+    the images must agree bit for bit, per frame and as batch kinds."""
+    f = ph.config_frame(2)
+    arr = ph.to_fp32(f.rf)
+    dev = torch.from_numpy(arr).cuda()
+    for mirror in (0, hd.FLAG_MIRROR):
+        fast = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, flags=mirror)
+        tested = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, flags=mirror | hd.FLAG_FORCE_CHECK)
+        assert fast.info().lds_bytes == tested.info().lds_bytes
+        info = fast.info()
+        for k in (1, 3, 6):
+            a = fast.beamform(dev, k)
+            b = tested.beamform(dev, k)
+            assert torch.equal(a, b), "per-frame k=%d mirror=%d" % (k, mirror)
+            outs = [torch.empty_like(a) for _ in range(2)]
+            bt = hd.Batch(max_frames=2, max_units=2 * info.n_tiles, max_lds_bytes=info.lds_bytes)
+            bt.set([fast, tested], [dev, dev], [k, k], outs)
+            bt.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(outs[0], a) and torch.equal(outs[1], a), "batch k=%d mirror=%d" % (k, mirror)
+            bt.close()
+            say("direct rows vs register staging mirror=%d k=%d: equal" % (mirror, k))
+        fast.close()
+        tested.close()

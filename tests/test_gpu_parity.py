@@ -194,6 +194,9 @@ def test_t0_irregular_stride_and_scale(hd):
 
 
 def test_plain_and_forced_check_modes(hd):
+    """FORCE_CHECK stages every row through registers and tests every delay;
+    the default plan copies the rows of tiles inside the record straight into
+    LDS and tests nothing there -- the images agree bit for bit."""
     f = ph.make_frame(24, 400, 33, 29, n_points=5, n_lines=1, seed=8)
     arr = ph.to_fp32(f.rf)
     base = hd.Plan(f.geometry, f.grid, 400, "f32", max_order=6)
