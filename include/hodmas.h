@@ -101,10 +101,10 @@ typedef struct {
 } hodmas_grid;
 
 /* RF storage.  frame_max is any positive bound on |sample| after
- * dequantisation (0 means 1).  FP16 and int16 samples are divided by it as the
- * kernel widens them, and the result is multiplied back, so its value changes
- * only rounding; FP32 samples are used as stored (e_k is of degree one in the
- * samples) and frame_max is not used for them. */
+ * dequantisation (0 means 1).  int16 codes are dequantised and divided by it
+ * as the kernel widens them, and the result is multiplied back, so its value
+ * changes only rounding; FP32 and FP16 samples are used as stored (e_k is of
+ * degree one in the samples) and frame_max is not used for them. */
 typedef struct {
     int32_t dtype;               /* hodmas_dtype */
     int32_t n_samples;           /* S, samples per channel */

@@ -170,6 +170,11 @@ hodmas_status build_tables(hodmas_plan_s* p)
     } catch (const std::bad_alloc&) {
         return HODMAS_ENOMEM;
     }
+    // FP32 / FP16 rows are copied straight into LDS through one buffer
+    // resource over the frame, whose range is a 32-bit byte count
+    const int64_t esz = p->rf.dtype == HODMAS_F32 ? 4 : 2;
+    const bool copies = p->rf.dtype == HODMAS_I16 ||
+                        int64_t(n) * p->rf.channel_stride * esz < (int64_t(1) << 31);
     const int chunk = p->tiling.chunk;
     const int split = p->tiling.split;
     int32_t max_window = 2;
@@ -218,9 +223,11 @@ hodmas_status build_tables(hodmas_plan_s* p)
             }
             // every staged row -- `window` samples from the element's first --
             // must lie inside the record for the untested path, which copies
-            // rows without bounds (FP32) and tests no delay
+            // FP32 and FP16 rows without bounds and tests no delay; so must
+            // the whole record inside one 32-bit buffer range
             for (int i = 0; i < n && !check; ++i)
                 check = act[i] && (wlo[i] < 0 || int64_t(wlo[i]) + window > S);
+            check = check || !copies;
             td.n_active = n_active;
             td.window = window;
             td.check = check ? 1 : 0;
@@ -373,10 +380,10 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         }
     }
     p->lds_bytes = std::max<int64_t>(staged_bytes(p->tiling.chunk, p->max_window, rows), reduce_bytes);
-    // FP16 / int16: widened samples are normalised by frame_max and the result
-    // scaled back; FP32 samples are used as stored, so the kernel may copy
-    // them into LDS untouched
-    const double fm = rf->frame_max > 0.f && rf->dtype != HODMAS_F32 ? (double)rf->frame_max : 1.0;
+    // int16: dequantised codes are normalised by frame_max and the result
+    // scaled back; FP32 and FP16 samples are used as stored (e_k is of degree
+    // one in the samples), so the kernel may copy their rows into LDS untouched
+    const double fm = rf->frame_max > 0.f && rf->dtype == HODMAS_I16 ? (double)rf->frame_max : 1.0;
     const double dq = rf->dtype == HODMAS_I16 ? (double)rf->dequant_scale : 1.0;
     p->in_scale = (float)(dq / fm);
     p->out_scale = (float)fm;
@@ -417,9 +424,6 @@ FrameArgs hodmas::frame_args(const hodmas_plan_s* plan, const void* rf_dev, floa
     a.dzs = plan->dzs;
     a.in_scale = plan->in_scale;
     a.out_scale = plan->out_scale;
-    a.direct = plan->rf.dtype == HODMAS_F32 &&
-               int64_t(plan->geom.n_elements) * plan->rf.channel_stride * 4 < (int64_t(1) << 31);
-    a.pad = 0;
     return a;
 }
 

@@ -30,12 +30,8 @@ struct FrameArgs {
     int32_t n_elements;      // array elements (the coherence factor's N)
     int32_t block;           // threads per workgroup: tile_x * tile_z * split
     double x0s, dxs, z0s, dzs;  // grid in samples
-    float in_scale;          // stored value -> kernel value (dequant / frame_max; 1 for FP32)
-    float out_scale;         // kernel result -> image units (frame_max; 1 for FP32)
-    // FP32 record of fewer than 2^31 bytes: tiles whose sample rows lie inside
-    // the record stage them straight from memory into LDS
-    int32_t direct;
-    int32_t pad;
+    float in_scale;          // stored value -> kernel value (int16: dequant / frame_max, else 1)
+    float out_scale;         // kernel result -> image units (int16: frame_max, else 1)
 };
 
 // Output images of the all-orders kernel: img[k-1] receives order k.

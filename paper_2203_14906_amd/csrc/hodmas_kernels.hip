@@ -127,10 +127,20 @@ __device__ __forceinline__ float lds_at(const float* __restrict__ lds, int addr)
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(lds) + addr);
 }
 
-// Linear interpolation between the two staged samples.
+// Linear interpolation between the two staged samples.  HALF: the LDS words
+// hold FP16 samples in their low halves (rows copied straight from an FP16
+// record); the mixed-precision FMA widens them, exactly, as it interpolates,
+// in the same two instructions.
+template <bool HALF = false>
 __device__ __forceinline__ float interp(const Tap& p, float s0, float s1)
 {
-    return __builtin_fmaf(p.f, s1 - s0, s0);
+    if constexpr (HALF) {
+        const float h0 = (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_bit_cast(unsigned, s0));
+        const float h1 = (float)__builtin_bit_cast(_Float16, (unsigned short)__builtin_bit_cast(unsigned, s1));
+        return __builtin_fmaf(p.f, h1, __builtin_fmaf(-p.f, h0, h0));
+    } else {
+        return __builtin_fmaf(p.f, s1 - s0, s0);
+    }
 }
 
 // y^1 .. y^K of the signed K-th root of v.
@@ -265,18 +275,22 @@ __device__ __forceinline__ void stage_chunk(const FrameArgs& A, ConstStage st, i
     }
 }
 
-// FP32 tiles whose rows lie inside the record (the plan marks the others as
-// tested) copy each row from memory straight into LDS: buffer loads that write
-// LDS, one per 64 samples, through one buffer resource over the whole frame,
-// with the row's start in the scalar offset.  One vector pass forms 64 rows'
-// offsets (lane j: row j), so a row then costs one lane read, scalar work and
-// one load per wave -- no vector registers in flight, no conversion and no LDS
-// store, where the general staging above spends several vector instructions
-// per row.
-template <int M>
+// FP32 and FP16 tiles whose rows lie inside the record (the plan marks the
+// others as tested) copy each row from memory straight into LDS: buffer loads
+// that write LDS, one per 64 samples, through one buffer resource over the
+// whole frame, with the row's start in the scalar offset.  One vector pass
+// forms 64 rows' offsets (lane j: row j), so a row then costs one lane read,
+// scalar work and one load per wave -- no vector registers in flight, no
+// conversion and no LDS store, where the general staging above spends several
+// vector instructions per row.  An FP16 sample lands, zero-extended, in the
+// low half of its LDS word (the layout of FP32 rows); the interpolation
+// widens it.
+template <int DT, int M>
 __device__ __forceinline__ void stage_direct(const FrameArgs& A, ConstStage st, int nch, int window,
                                              float* __restrict__ lds, int wave, int nwaves, int lane)
 {
+    static_assert(DT == HODMAS_F32 || DT == HODMAS_F16, "direct copies move 4- or 2-byte samples");
+    constexpr int esz = DT == HODMAS_F32 ? 4 : 2;
     using LdsPtr = __attribute__((address_space(3))) void*;
     const int rows = M * nch;
     const int per_wave = (rows + nwaves - 1) / nwaves;
@@ -285,7 +299,7 @@ __device__ __forceinline__ void stage_direct(const FrameArgs& A, ConstStage st, 
     const int stride = row_stride(window);
     if (wave == 0 && lane < 2 * M)
         lds[(lane >> 1) * nch * stride + window + (lane & 1)] = 0.f;
-    const int bytes = A.n_elements * (int)A.stride * 4;   // below 2^31 when A.direct is set
+    const int bytes = A.n_elements * (int)A.stride * esz;   // below 2^31: the plan tests every tile otherwise
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(A.rf), (short)0, bytes, kBufferFlags);
     const Global<const int> ent = global_ptr(reinterpret_cast<const int*>(st));
@@ -295,14 +309,18 @@ __device__ __forceinline__ void stage_direct(const FrameArgs& A, ConstStage st, 
         const int src = mirrored ? j - nch : j;
         const int elem = ent[2 * src];
         const int ch = mirrored ? A.n_elements - 1 - elem : elem;
-        const int my_off = (ch * (int)A.stride + ent[2 * src + 1]) * 4;
+        const int my_off = (ch * (int)A.stride + ent[2 * src + 1]) * esz;
         const int cend = __builtin_amdgcn_readfirstlane(min(s1 - c, 64));
         for (int b = 0; b < window; b += 64) {
             if (b + lane < window) {
                 for (int m = 0; m < cend; ++m) {
                     const int soff = __builtin_amdgcn_readlane(my_off, m);
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsPtr)(lds + (c + m) * stride + b), 4,
-                                                             (b + lane) * 4, soff, 0, 0);
+                    if constexpr (DT == HODMAS_F32)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsPtr)(lds + (c + m) * stride + b), 4,
+                                                                 (b + lane) * 4, soff, 0, 0);
+                    else
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LdsPtr)(lds + (c + m) * stride + b), 2,
+                                                                 (b + lane) * 2, soff, 0, 0);
                 }
             }
         }
@@ -350,7 +368,7 @@ __device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[
 // With M == 2 each delay also serves the lane's mirror pixel, whose samples
 // sit `moff` bytes further on in the LDS (the mirrored rows).  `zero`: the
 // LDS byte address of the zero pair (CHECK).
-template <int K, bool CF, bool COMP, bool CHECK, int M, int NS = n_sums<K, CF>()>
+template <int K, bool CF, bool COMP, bool CHECK, bool HALF, int M, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], float u2, float q,
                                               const float* __restrict__ lds, int moff, int zero, float (&s)[M][NS],
                                               float (&P)[M][NS], bool more, ConstEntry En,
@@ -378,7 +396,7 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
     for (int mm = 0; mm < M; ++mm) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
-            v[mm][m] = interp(tp[m], s0[mm][m], s1[mm][m]);
+            v[mm][m] = interp<HALF>(tp[m], s0[mm][m], s1[mm][m]);
     }
     // emits nothing: makes the samples (hence this group's LDS waits)
     // complete before the scalar loads below are issued
@@ -421,7 +439,7 @@ __device__ __forceinline__ void after_group(int& groups, float (&s)[M][NS], floa
 // The n elements of this wave's split group in one staged chunk (their
 // constants stored contiguously), four at a time; two constant sets alternate
 // so nothing is copied between them.
-template <int K, bool CF, bool COMP, bool CHECK, int M, int NS = n_sums<K, CF>()>
+template <int K, bool CF, bool COMP, bool CHECK, bool HALF, int M, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, float q,
                                                  const float* __restrict__ lds, int moff, int zero, float (&s)[M][NS],
                                                  float (&c)[M][NS])
@@ -440,13 +458,13 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK, M>(ea, u2, q, lds, moff, zero, s, P, more_a, E + sl + 4, eb);
+            process_group<K, CF, COMP, CHECK, HALF, M>(ea, u2, q, lds, moff, zero, s, P, more_a, E + sl + 4, eb);
             after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK, M>(eb, u2, q, lds, moff, zero, s, P, more_b, E + sl + 4, ea);
+            process_group<K, CF, COMP, CHECK, HALF, M>(eb, u2, q, lds, moff, zero, s, P, more_b, E + sl + 4, ea);
             after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_b)
@@ -462,7 +480,7 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
         for (int mm = 0; mm < M; ++mm) {
             float T[NS];
             const int addr = tp.addr + mm * moff;
-            terms<K, CF>(interp(tp, lds_at(lds, addr), lds_at(lds, addr + 4)), T);
+            terms<K, CF>(interp<HALF>(tp, lds_at(lds, addr), lds_at(lds, addr + 4)), T);
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
                 if (COMP)
@@ -511,6 +529,9 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
                                              float* __restrict__ lds)
 {
     constexpr int NS = n_sums<K, CF>();
+    // rows copied straight into LDS (FP32, FP16) unless the tile is range-tested
+    constexpr bool kDirect = !CHECK && (DT == HODMAS_F32 || DT == HODMAS_F16);
+    constexpr bool kHalf = kDirect && DT == HODMAS_F16;
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
     const int nwaves = A.block >> 6;
@@ -558,8 +579,8 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();                       // previous readers of the LDS are done
-        if (DT == HODMAS_F32 && !CHECK && A.direct)
-            stage_direct<M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        if constexpr (kDirect)
+            stage_direct<DT, M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         else
             stage_chunk<DT, M>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
@@ -570,7 +591,7 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
         for (int h = 0; h < g; ++h)
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
-        accumulate_chunk<K, CF, COMP, CHECK, M>(E + c0 + goff, ng, u2, q, lds, moff, zero, s, c);
+        accumulate_chunk<K, CF, COMP, CHECK, kHalf, M>(E + c0 + goff, ng, u2, q, lds, moff, zero, s, c);
     }
 
     if (A.split > 1) {
@@ -786,7 +807,7 @@ __device__ __forceinline__ void terms_all(float v, float (&T)[kSums])
     }
 }
 
-template <int KMAX, bool COMP, bool CHECK>
+template <int KMAX, bool COMP, bool CHECK, bool HALF>
 __device__ __forceinline__ void process_group_all(const hodmas_chan_entry (&e)[4], float u2, float q,
                                                   const float* __restrict__ lds, int zero, float (&s)[kSums],
                                                   float (&P)[kSums], bool more, ConstEntry En,
@@ -809,7 +830,7 @@ __device__ __forceinline__ void process_group_all(const hodmas_chan_entry (&e)[4
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        v[m] = interp(tp[m], s0[m], s1[m]);
+        v[m] = interp<HALF>(tp[m], s0[m], s1[m]);
     asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]) : "memory");
     if (more)
         load_group(En, en);
@@ -845,7 +866,7 @@ __device__ __forceinline__ void flush_all(float (&s)[kSums], float (&c)[kSums], 
     }
 }
 
-template <int KMAX, bool COMP, bool CHECK>
+template <int KMAX, bool COMP, bool CHECK, bool HALF>
 __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float u2, float q,
                                                      const float* __restrict__ lds, int zero, float (&s)[kSums],
                                                      float (&c)[kSums])
@@ -861,14 +882,14 @@ __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float 
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group_all<KMAX, COMP, CHECK>(ea, u2, q, lds, zero, s, P, more_a, E + sl + 4, eb);
+            process_group_all<KMAX, COMP, CHECK, HALF>(ea, u2, q, lds, zero, s, P, more_a, E + sl + 4, eb);
             if (COMP && (++groups & 7) == 0)
                 flush_all<KMAX, COMP>(s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group_all<KMAX, COMP, CHECK>(eb, u2, q, lds, zero, s, P, more_b, E + sl + 4, ea);
+            process_group_all<KMAX, COMP, CHECK, HALF>(eb, u2, q, lds, zero, s, P, more_b, E + sl + 4, ea);
             if (COMP && (++groups & 7) == 0)
                 flush_all<KMAX, COMP>(s, c, P);
             sl += 4;
@@ -882,7 +903,7 @@ __device__ __forceinline__ void accumulate_chunk_all(ConstEntry E, int n, float 
         if (CHECK)
             redirect(tp, e, zero);
         float T[kSums];
-        terms_all<KMAX>(interp(tp, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
+        terms_all<KMAX>(interp<HALF>(tp, lds_at(lds, tp.addr), lds_at(lds, tp.addr + 4)), T);
 #pragma unroll
         for (int j = 0; j < kSums; ++j) {
             if (!sum_needed(j, KMAX))
@@ -914,6 +935,8 @@ __device__ __forceinline__ void orders_tile(const FrameArgs& A, const OrderImage
                                             float* __restrict__ lds)
 {
     constexpr int NT = kSums;
+    constexpr bool kDirect = !CHECK && (DT == HODMAS_F32 || DT == HODMAS_F16);
+    constexpr bool kHalf = kDirect && DT == HODMAS_F16;
     const int tid = threadIdx.x;
     const int npix = A.block / A.split;
     const int nwaves = A.block >> 6;
@@ -944,8 +967,8 @@ __device__ __forceinline__ void orders_tile(const FrameArgs& A, const OrderImage
     for (int c0 = 0; c0 < td.n_active; c0 += A.chunk) {
         const int nch = min(A.chunk, td.n_active - c0);
         __syncthreads();
-        if (DT == HODMAS_F32 && !CHECK && A.direct)
-            stage_direct<1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
+        if constexpr (kDirect)
+            stage_direct<DT, 1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         else
             stage_chunk<DT, 1>(A, St + c0, nch, td.window, lds, wave, nwaves, lane);
         __syncthreads();
@@ -953,7 +976,7 @@ __device__ __forceinline__ void orders_tile(const FrameArgs& A, const OrderImage
         for (int h = 0; h < g; ++h)
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
-        accumulate_chunk_all<KMAX, COMP, CHECK>(E + c0 + goff, ng, u2, q, lds, zero_offset(td.window), s, c);
+        accumulate_chunk_all<KMAX, COMP, CHECK, kHalf>(E + c0 + goff, ng, u2, q, lds, zero_offset(td.window), s, c);
     }
     if (A.split > 1) {
         __syncthreads();
