@@ -21,6 +21,9 @@ sum over element subsets of signed k-th roots of the delayed samples).
 - The FP32 staging the step uses (rows copied straight from memory into LDS)
   against the register path with every delay tested (FLAG_FORCE_CHECK), on
   the step's frame, paired and unpaired, per frame and batched: bit for bit.
+  The same for FP16 rows, whose direct path interpolates the stored halves
+  with the mixed-precision FMA: within 1e-6 of the register path (the two
+  round the interpolation differently) and of the oracle on the same values.
 """
 import sys
 
@@ -257,5 +260,32 @@ def test_direct_rows_equal_register_staging(hd):
             assert torch.equal(outs[0], a) and torch.equal(outs[1], a), "batch k=%d mirror=%d" % (k, mirror)
             bt.close()
             say("direct rows vs register staging mirror=%d k=%d: equal" % (mirror, k))
+        fast.close()
+        tested.close()
+
+
+def test_direct_fp16_rows_against_register_staging(hd):
+    """FP16 rows copied straight into LDS (low halves of LDS words, widened by
+    the interpolation) against FLAG_FORCE_CHECK plans (rows widened through
+    registers, every delay tested), config-2 geometry with FP16 storage."""
+    f = ph.config_frame(2)
+    half = ph.to_fp16(f.rf)
+    dev = torch.from_numpy(half).cuda()
+    for mirror in (0, hd.FLAG_MIRROR):
+        fast = hd.Plan(f.geometry, f.grid, half.shape[1], "f16", max_order=6, flags=mirror)
+        tested = hd.Plan(f.geometry, f.grid, half.shape[1], "f16", max_order=6, flags=mirror | hd.FLAG_FORCE_CHECK)
+        for k in (1, 3, 6):
+            a = fast.beamform(dev, k).cpu().numpy().astype(np.float64)
+            b = tested.beamform(dev, k).cpu().numpy().astype(np.float64)
+            # the two round each interpolated sample differently; where a
+            # sample sits on a zero crossing its root can flip, so those few
+            # pixels are counted and the rest compared
+            off = np.abs(a - b) > 1e-5 * np.abs(b).max()
+            keep = ~off
+            err = rel_l2(a[keep], b[keep])
+            say("fp16 direct vs register staging mirror=%d k=%d: rel L2 %.2e, %d pixels apart"
+                % (mirror, k, err, int(off.sum())))
+            assert off.mean() <= 1e-4
+            assert err <= 1e-6
         fast.close()
         tested.close()
