@@ -18,6 +18,10 @@ sum over element subsets of signed k-th roots of the delayed samples).
   the bar -- elsewhere the kernel adds no more than its own 2e-5 to it).
 - The reduced-precision workload (256 elements, 1024x1024, int16 and FP16)
   on full images at every order, unpaired and paired, against both oracles.
+- Pixel by pixel, beside the relative L2 bars: the step's first two frames
+  (every pixel) and the reduced-precision workload (every 16th row) stay
+  within a per-pixel bound from a running error analysis of the kernel's
+  float32 steps (tests/error_bound.py) at every order.
 - The FP32 staging the step uses (rows copied straight from memory into LDS)
   against the register path with every delay tested (FLAG_FORCE_CHECK), on
   the step's frame, paired and unpaired, per frame and batched: bit for bit.
@@ -26,10 +30,12 @@ sum over element subsets of signed k-th roots of the delayed samples).
   round the interpolation differently) and of the oracle on the same values.
 """
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
+import error_bound as EB
 from oracle import oracle as O
 from paper_2203_14906_amd import phantom as ph
 from sign_band import MAX_FLAGGED_SHARE, SignBand, plan_eps
@@ -39,6 +45,7 @@ pytestmark = pytest.mark.gpu
 
 ORDERS = (1, 2, 3, 4, 5, 6)
 BENCH_FRAMES = 8
+BOUND_FRAMES = 2       # bench frames also checked pixel by pixel against the error bound
 STORAGE_BAR = 2e-3     # reduced-precision storage against the unquantised FP64 RF
 KERNEL_BAR = {"f32": 1e-5, "f16": 2e-5, "i16": 2e-5}   # against the same stored values
 
@@ -95,6 +102,28 @@ def config2():
     return frames, oracle_image, band
 
 
+@pytest.fixture(scope="module")
+def config2_bounds(hd, config2):
+    """Per-pixel error bounds (tests/error_bound.py) of the first
+    BOUND_FRAMES bench frames at every order, for FP32 storage, with the
+    delay allowance of both plan forms (the larger of the two): {(b, k): [nz][nx]}."""
+    frames = config2[0]
+    geom, grid = frames[0].geometry, frames[0].grid
+    S = frames[0].rf.shape[1]
+    eps = 0.0
+    for fl in (0, hd.FLAG_MIRROR):
+        plan = hd.Plan(geom, grid, S, "f32", max_order=max(ORDERS), flags=fl | hd.FLAG_HOST_ONLY)
+        eps = max(eps, plan_eps(plan, geom, grid, mirror=bool(fl)))
+        plan.close()
+
+    def one(b):
+        return EB.pixel_bounds(ph.to_fp32(frames[b].rf), geom, grid, ORDERS, eps)
+
+    with ThreadPoolExecutor(max_workers=BOUND_FRAMES) as pool:
+        per_frame = list(pool.map(one, range(BOUND_FRAMES)))
+    return {(b, k): per_frame[b][k] for b in range(BOUND_FRAMES) for k in ORDERS}
+
+
 def band_error(sb, img, k, ref, what):
     """Relative L2 from the oracle with sign-change pixels taken from their
     band; the plain figure beside it."""
@@ -124,7 +153,7 @@ def run_batch_per_order(hd, plan, devs, grid, orders):
 
 
 @pytest.mark.parametrize("pairing", ["mirror", "unpaired"])
-def test_bench_step_config2_every_order(hd, config2, pairing):
+def test_bench_step_config2_every_order(hd, config2, config2_bounds, pairing):
     frames, oracle_image, band = config2
     geom, grid = frames[0].geometry, frames[0].grid
     S = frames[0].rf.shape[1]
@@ -142,7 +171,7 @@ def test_bench_step_config2_every_order(hd, config2, pairing):
     flagged = [band(("f32", b), arrs[b], eps).flagged for b in range(len(arrs))]
     say("  band half-width %.2e samples; sign-change pixels per frame %s" % (eps, flagged))
     for k in ORDERS:
-        worst, worst_plain, worst_inf = 0.0, 0.0, 0.0
+        worst, worst_plain, worst_inf, worst_q = 0.0, 0.0, 0.0, 0.0
         for b, dev in enumerate(devs):
             own = plan.beamform(dev, k).cpu().numpy()
             assert np.array_equal(got[k][b], own), "k=%d frame %d: batch differs from its own launch" % (k, b)
@@ -151,8 +180,13 @@ def test_bench_step_config2_every_order(hd, config2, pairing):
             worst, worst_plain = max(worst, err), max(worst_plain, plain)
             worst_inf = max(worst_inf, linf(got[k][b].astype(np.float64), o))
             assert err <= KERNEL_BAR["f32"], "k=%d frame %d rel L2 %.3e" % (k, b, err)
-        say("  k=%d: 8 full images, worst rel L2 %.2e from the band (plain %.2e), worst max|err|/max|o| %.2e"
-            % (k, worst, worst_plain, worst_inf))
+            if b < BOUND_FRAMES:
+                q = EB.worst_ratio(got[k][b], o, config2_bounds[(b, k)])
+                worst_q = max(worst_q, q)
+                assert q <= 1.0, "k=%d frame %d: a pixel reaches %.2f of its error bound" % (k, b, q)
+        say("  k=%d: 8 full images, worst rel L2 %.2e from the band (plain %.2e), worst max|err|/max|o| %.2e; "
+            "frames 0-%d pixel by pixel: at most %.3f of the bound" % (k, worst, worst_plain, worst_inf,
+                                                                       BOUND_FRAMES - 1, worst_q))
     plan.close()
 
 
@@ -218,6 +252,8 @@ def test_reduced_workload_full_images_both_oracles(hd, dtype):
                   eps=max(plan_eps(plans["unpaired"], f.geometry, f.grid),
                           plan_eps(plans["mirror"], f.geometry, f.grid, mirror=True)))
     say("  config 3 %s: band half-width %.2e samples, %d sign-change pixels" % (dtype, sb.eps, sb.flagged))
+    rows = np.arange(0, f.grid.nz, 16)
+    bounds = EB.pixel_bounds(arr, f.geometry, f.grid, ORDERS, sb.eps, dequant_scale=scale, rows=rows)
     for k in ORDERS:
         same = O.beamform(arr, f.geometry, f.grid, k, dequant_scale=scale)
         pre = O.beamform(f.rf, f.geometry, f.grid, k)
@@ -226,9 +262,11 @@ def test_reduced_workload_full_images_both_oracles(hd, dtype):
             img = plan.beamform(dev, k).cpu().numpy().astype(np.float64)
             e_same, _ = band_error(sb, img, k, same, "config 3 %s %s" % (dtype, name))
             e_pre = rel_l2(img, pre)
-            say("  config 3 %s %s k=%d: vs same stored values %.2e, vs unquantised RF %.2e (storage alone %.2e)"
-                % (dtype, name, k, e_same, e_pre, store))
+            q = EB.worst_ratio(img[rows], same[rows], bounds[k])
+            say("  config 3 %s %s k=%d: vs same stored values %.2e, vs unquantised RF %.2e (storage alone %.2e); "
+                "every 16th row pixel by pixel: at most %.3f of the bound" % (dtype, name, k, e_same, e_pre, store, q))
             assert e_same <= KERNEL_BAR[dtype]
+            assert q <= 1.0, "config 3 %s %s k=%d: a pixel reaches %.2f of its error bound" % (dtype, name, k, q)
             check_storage_bar(dtype, k, e_pre, store)
     for p in plans.values():
         p.close()
