@@ -107,6 +107,8 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        _copy_256mib(torch)
     {"plain": bench_plain, "small": bench_small, "reduced": bench_reduced, "batch": bench_batch,
      "serve": bench_serve, "display": bench_display}[args.workload](args, torch)
 
@@ -155,6 +157,17 @@ def _issued_slots(kernel, pixch, seconds):
     return None
 
 
+def _copy_256mib(torch):
+    """A plain 256 MiB device-to-device copy, three times: the known byte
+    count that HBM counter readings are scaled by."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def _events(torch, n):
     return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
 
@@ -176,14 +189,6 @@ def bench_plain(args, torch):
     out = [torch.empty((grid.nz, grid.nx), dtype=torch.float32, device=dev) for _ in frames]
     stream = torch.cuda.current_stream()
     pixch = grid.nx * grid.nz * n_el
-
-    if args.calibrate_copy:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     # A step beamforms the B resident frames at every order.  By default each
     # order is one persistent batched launch over the B frames (their work
