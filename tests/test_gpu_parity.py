@@ -2,15 +2,19 @@
 same seeded inputs.  Tolerances (relative L2 over the compared pixels):
 1e-5 for float32 storage; 2e-3 for float16 / int16 storage, where the oracle is
 fed the same stored values (widened exactly) -- the kernel's own arithmetic is
-additionally held to 2e-5 there."""
+additionally held to 2e-5 there.  The full-image cases also hold every pixel
+to the per-pixel error bound of tests/error_bound.py (delay allowance: the
+plan's own float32 delay-error bound)."""
 import ctypes
 import sys
 
 import numpy as np
 import pytest
 
+import error_bound as EB
 from oracle import oracle as O
 from paper_2203_14906_amd import phantom as ph
+from sign_band import plan_eps
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -59,6 +63,13 @@ def oracle_image(arr, scale, geom, grid, order, pixels=None):
                       pixels=pixels)
 
 
+def check_pixels(g, o, bounds, k, what):
+    """Every pixel within its error bound."""
+    q = EB.worst_ratio(g, o, bounds[k])
+    say("%-48s at most %.3f of the pixel bound" % (what, q))
+    assert q <= 1.0, "%s: a pixel reaches %.2f of its error bound" % (what, q)
+
+
 def check(err, dtype, what):
     say("%-48s rel L2 %.3e" % (what, err))
     if dtype == "f32":
@@ -76,11 +87,13 @@ def test_config_full_image_fp32(hd, cfg):
     plan = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=max(orders))
     say("config %d: %d x %d grid, N=%d, S=%d, tiling %s" % (cfg, f.grid.nx, f.grid.nz, arr.shape[0],
         arr.shape[1], tuple(getattr(plan.info().tiling, n) for n in ("tile_x", "tile_z", "split", "chunk"))))
+    bounds = EB.pixel_bounds(arr, f.geometry, f.grid, orders, plan_eps(plan, f.geometry, f.grid))
     for k in orders:
         say("config %d order %d" % (cfg, k))
         g = gpu_image(hd, plan, arr, k)
         o = oracle_image(arr, 1.0, f.geometry, f.grid, k)
         check(rel_l2(g, o), "f32", "config %d f32 order %d" % (cfg, k))
+        check_pixels(g, o, bounds, k, "config %d f32 order %d" % (cfg, k))
     plan.close()
 
 
@@ -122,11 +135,14 @@ def test_small_ragged_frames(hd, tiling, dtype):
     arr, scale = stored(f.rf, dtype, seed=17)
     plan = hd.Plan(f.geometry, grid, arr.shape[1], dtype, max_order=6, dequant_scale=scale,
                    tiling=tiling)
+    bounds = EB.pixel_bounds(arr, f.geometry, grid, range(1, 7), plan_eps(plan, f.geometry, grid),
+                             dequant_scale=scale if dtype == "i16" else None)
     for k in range(1, 7):
         say("small frame %s tiling %s order %d" % (dtype, tiling, k))
         g = gpu_image(hd, plan, arr, k)
         o = oracle_image(arr, scale, f.geometry, grid, k)
         check(rel_l2(g, o), dtype, "small %s %s k=%d" % (dtype, tiling, k))
+        check_pixels(g, o, bounds, k, "small %s %s k=%d" % (dtype, tiling, k))
     plan.close()
 
 
