@@ -80,6 +80,11 @@ typedef enum {
                                          together with its mirror image about x = 0 from
                                          one delay (symmetric array and grid only, see
                                          hodmas_plan) */
+#define HODMAS_FLAG_NO_SHARE    0x40u /* compute every delay in full: no delays shared
+                                         along translated pixels (see hodmas_plan) */
+/* Reported in hodmas_plan_info.flags, never passed in: the plan's unpaired,
+ * unweighted tiles share delays along translated pixels (see hodmas_plan). */
+#define HODMAS_INFO_SHARED_DELAYS 0x10000u
 
 /* Linear array.  element_x_m == NULL means a centred uniform array,
  * x_i = (i - (n_elements-1)/2) * pitch_m.  The pointer is read during
@@ -138,6 +143,17 @@ typedef struct hodmas_plan_s* hodmas_plan_t;
  * length c/fs) and a tiling whose tile_x divides nx into an even number of
  * tile columns; hodmas_beamform then runs one workgroup per pair of mirror
  * tiles.  Images differ from the unpaired launch only in rounding.
+ * Delays along translated pixels (Eq. 1 depends on pixel x minus element x
+ * only): when consecutive elements are exactly four pixel columns apart
+ * (x_{i+1} - x_i = 4 dx_m to 1e-12), tiles are 16 columns wide with one
+ * element group, nx is a multiple of 16 and each tile's contributing elements
+ * are consecutive, an unpaired, unweighted plan's kernels compute, from
+ * order 2 on, one delay per lane for every four elements and take the other
+ * three from neighbouring lanes through 32 eight-byte LDS entries per row of
+ * 16 lanes (included in hodmas_plan_info.lds_bytes), unless that LDS would
+ * leave a one-frame launch needing more rounds of workgroups over the
+ * device's 256 CUs (HODMAS_INFO_SHARED_DELAYS in hodmas_plan_info.flags says
+ * which; HODMAS_FLAG_NO_SHARE turns it off).  Images differ only in rounding.
  * Errors: EINVAL (null pointer, non-positive or non-finite sizes/speeds, stride
  * < S, limits above exceeded, bad tiling, HODMAS_FLAG_MIRROR on an asymmetric
  * geometry or tiling), ENOMEM, EDEVICE. */

@@ -214,7 +214,7 @@ hodmas_status hodmas_batch_set(hodmas_batch_t b, const hodmas_plan_t* plans, con
                 return HODMAS_EINVAL;
             pixch += int64_t(p->grid.nx) * p->grid.nz * p->geom.n_elements;
             const int kind = hodmas::batch_kind(orders[f], p->rf.dtype, pairing, cf);
-            kl[kind] = std::max(kl[kind], p->lds_bytes);
+            kl[kind] = std::max(kl[kind], hodmas::launch_lds(p, orders[f]));
             for (int i = 0; i < n_units; ++i) {
                 const int t = pairing == 1 ? i : i / half * 2 * half + i % half;
                 const hodmas_tile_desc& td = p->tiles[t];

@@ -24,6 +24,10 @@ using hodmas::kPlanMagic;
 
 namespace {
 
+// Compute units of the MI355X, for the plan's estimate of workgroup rounds
+// (hodmas_plan may run with no device: HODMAS_FLAG_HOST_ONLY).
+constexpr int64_t kComputeUnits = 256;
+
 constexpr uint32_t kMagic = kPlanMagic;
 constexpr double kMaxDistanceSamples = 4194304.0;  // 2^22: delays stay exact-integer in float32
 
@@ -268,6 +272,41 @@ hodmas_status build_tables(hodmas_plan_s* p)
     return HODMAS_OK;
 }
 
+// Delays shared along translated pixels (unpaired, unweighted plans, in the
+// tiles that stay inside the record): the element pitch is exactly four pixel
+// columns of the grid, every tile is 16 columns wide and has one element group,
+// and each tile's contributing elements are consecutive, in index order.
+// The moved pixel's delay (four columns left of the tile's own pixels) is
+// formed from the tile's anchor like the others; it stays as accurate only
+// where the pixels lie deeper than a tile is wide, so tile rows above that
+// depth compute every delay (shared_first_row).
+int32_t shared_first_row(const hodmas_plan_s* p)
+{
+    const int tz = p->tiling.tile_z;
+    int32_t r = 0;
+    while (r < p->grid.nz && p->z0s + r * p->dzs < 16.0 * p->dxs)
+        r += tz;
+    return r;
+}
+
+int32_t shared_delay_step(const hodmas_plan_s* p)
+{
+    const int n = p->geom.n_elements;
+    const double step = 4.0 * p->grid.dx_m;
+    if ((p->flags & (HODMAS_FLAG_NO_SHARE | HODMAS_FLAG_MIRROR | HODMAS_FLAG_CF)) || p->tiling.tile_x != 16 ||
+        p->tiling.split != 1 ||
+        p->grid.nx % 16 != 0 || !(step > 0.0) || n < 2)
+        return 0;
+    for (int i = 0; i + 1 < n; ++i)
+        if (!(std::fabs(p->elem_x[i + 1] - p->elem_x[i] - step) <= 1e-12 * step))
+            return 0;
+    for (const hodmas_tile_desc& td : p->tiles)
+        for (int sl = 1; sl < td.n_active; ++sl)
+            if (p->stage[(size_t)td.first_entry + sl].channel != p->stage[(size_t)td.first_entry + sl - 1].channel + 1)
+                return 0;
+    return 4;
+}
+
 hodmas_status upload(hodmas_plan_s* p)
 {
     if (hipGetDevice(&p->device) != hipSuccess)
@@ -387,6 +426,28 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     const double dq = rf->dtype == HODMAS_I16 ? (double)rf->dequant_scale : 1.0;
     p->in_scale = (float)(dq / fm);
     p->out_scale = (float)fm;
+    p->shift = shared_delay_step(p);
+    p->shift_iz0 = shared_first_row(p);
+    p->lds_unshared = p->lds_bytes;
+    if (p->shift) {
+        // each row of 16 lanes passes delays through 32 (4 floor(delay), fraction) entries
+        const int32_t off = (int32_t)((staged_bytes(p->tiling.chunk, p->max_window, rows) + 7) / 8 * 8);
+        const int64_t with = std::max<int64_t>(p->lds_bytes, off + block / 16 * 32 * 8);
+        // The buffers take LDS; where that leaves fewer workgroups per CU and a
+        // one-frame launch then needs more rounds of workgroups over the CUs
+        // (a 1024^2 grid: 16 tiles per CU, 3 rounds at 6 per CU, 4 at 5), the
+        // lost round costs more than the shared delays save: keep every delay.
+        auto rounds = [&](int64_t lds) {
+            const int64_t per_cu = std::max<int64_t>(1, hodmas::kMaxLdsBytes / std::max<int64_t>(lds, 1));
+            return ceil_div((int64_t)p->tiles.size(), per_cu * kComputeUnits);
+        };
+        if (rounds(with) <= rounds(p->lds_bytes)) {
+            p->shift_off = off;
+            p->lds_bytes = with;
+        } else {
+            p->shift = 0;
+        }
+    }
     if (!(flags & HODMAS_FLAG_HOST_ONLY)) {
         st = upload(p);
         if (st != HODMAS_OK) {
@@ -424,6 +485,9 @@ FrameArgs hodmas::frame_args(const hodmas_plan_s* plan, const void* rf_dev, floa
     a.dzs = plan->dzs;
     a.in_scale = plan->in_scale;
     a.out_scale = plan->out_scale;
+    a.shift = plan->shift;
+    a.shift_iz0 = plan->shift_iz0;
+    a.shift_off = plan->shift_off;
     return a;
 }
 
@@ -447,7 +511,8 @@ hodmas_status hodmas_beamform(hodmas_plan_t plan, const void* rf_dev, int32_t or
     const bool comp = !(plan->flags & HODMAS_FLAG_ACC_PLAIN);
     const bool cf = (plan->flags & HODMAS_FLAG_CF) != 0;
     const bool mirror = (plan->flags & HODMAS_FLAG_MIRROR) != 0;
-    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, cf, mirror, plan->lds_bytes, stream);
+    int rc = hodmas::launch_frame(a, order, plan->rf.dtype, comp, cf, mirror, hodmas::launch_lds(plan, order),
+                                  stream);
     if (cur != plan->device)
         (void)hipSetDevice(cur);
     return rc == 0 ? HODMAS_OK : HODMAS_EDEVICE;
@@ -545,6 +610,8 @@ hodmas_status hodmas_plan_get_info(hodmas_plan_t plan, hodmas_plan_info* info)
     info->lds_bytes = plan->lds_bytes;
     info->table_bytes = plan->table_bytes;
     info->flags = plan->flags;
+    if (plan->shift)
+        info->flags |= HODMAS_INFO_SHARED_DELAYS;
     return HODMAS_OK;
 }
 

@@ -29,6 +29,9 @@ struct FrameArgs {
     int32_t n_tiles;
     int32_t n_elements;      // array elements (the coherence factor's N)
     int32_t block;           // threads per workgroup: tile_x * tile_z * split
+    int32_t shift;           // 4: element pitch = 4 pixel columns, delays shared along translated pixels; else 0
+    int32_t shift_iz0;       // ... in the tiles whose first row is at least this one
+    int32_t shift_off;       // LDS byte offset of the rows' delay buffers (after the staged rows)
     double x0s, dxs, z0s, dzs;  // grid in samples
     float in_scale;          // stored value -> kernel value (int16: dequant / frame_max, else 1)
     float out_scale;         // kernel result -> image units (int16: frame_max, else 1)
@@ -109,6 +112,8 @@ struct hodmas_plan_s {
     int32_t max_window = 0;
     int64_t lds_bytes = 0;
     float in_scale = 1.f, out_scale = 1.f;
+    int32_t shift = 0, shift_iz0 = 0, shift_off = 0;   // FrameArgs::shift, ::shift_iz0, ::shift_off
+    int64_t lds_unshared = 0;             // lds_bytes without the delay buffers
     int device = -1;
     hodmas_tile_desc* d_tiles = nullptr;
     hodmas_chan_entry* d_entries = nullptr;
@@ -117,6 +122,15 @@ struct hodmas_plan_s {
 };
 
 namespace hodmas {
+
+// Dynamic LDS of a launch of `plan` at `order`: the kernels share delays
+// along translated pixels from order 2 on (at order 1 the buffer's round
+// trip costs more than the delays it saves), so order 1 runs without the
+// buffers.
+inline int64_t launch_lds(const hodmas_plan_s* plan, int order)
+{
+    return plan->shift && order >= 2 ? plan->lds_bytes : plan->lds_unshared;
+}
 
 // Kernel arguments of one frame under `plan`.
 FrameArgs frame_args(const hodmas_plan_s* plan, const void* rf_dev, float* image_dev);

@@ -96,7 +96,7 @@ struct Tap {
     int addr;    // LDS byte address of the sample before the delay
 };
 
-__device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, float q)
+__device__ __forceinline__ Tap locate_at(const hodmas_chan_entry& e, float u2, float q, int off)
 {
     Tap p;
     const float num = __builtin_fmaf(u2, e.a, q);
@@ -109,8 +109,59 @@ __device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, floa
     int fl;
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(fl) : "v"(p.t));
     p.f = __builtin_amdgcn_fractf(p.t);
-    p.addr = (fl << 2) + e.off;
+    p.addr = (fl << 2) + off;
     return p;
+}
+
+__device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, float q)
+{
+    return locate_at(e, u2, q, e.off);
+}
+
+// Delays shared along translated pixels.  When the element pitch of a uniform
+// linear array is SH pixel columns, the pixel in column x sees element i + 1
+// at exactly the delay at which the pixel in column x - SH sees element i
+// (Eq. 1 depends on the pixel's x minus the element's x only).  The 16 lanes
+// of a tile row are 16 neighbouring columns, so for elements i + s, s = 1..3,
+// a lane takes element i's delay from the lane s*SH columns to its left -- or,
+// in the row's first s*SH lanes, from F: element i + 3's delay at the pixel
+// 16 - 3*SH columns to the left, which is also element i + 4's at the lane's
+// own pixel (the next group's first element).  A group of four elements then
+// computes one delay per lane instead of four, and passes the others between
+// the lanes of a row through a 32-entry LDS buffer: F in entries [0, 16),
+// element i's own delays in [16, 32), so element i + s of lane j is entry
+// 16 + j - s*SH.  The shared quantities are 4 floor(delay) as an absolute
+// sample index and the fraction; each element adds the byte offset that its
+// LDS row gives sample 0.
+struct XF {
+    int x;      // 4 floor(delay), absolute sample index
+    float f;    // fraction of the delay
+};
+
+struct Shared {
+    int x;      // the group's first element at the lane's pixel
+    float f;
+    XF* buf;    // the lane's entry j of its row's buffer
+};
+
+// Orders the LDS accesses of one wave that exchange data between its lanes:
+// a wave's LDS instructions complete in issue order, so keeping the compiler
+// from moving them across this point is all that is needed.
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Byte offset of sample 0 in the LDS rows of four consecutive staged slots
+// (slot, ..., slot + 3 of the chunk whose staging entries start at S): the
+// sample at absolute index j of slot m sits at 4 j + ro[m].
+__device__ __forceinline__ void load_rowoff(ConstStage S, int slot, int stride, int (&ro)[4])
+{
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        ro[m] = 4 * ((slot + m) * stride - load_const(S, slot + m).first_sample);
 }
 
 // Tiles whose delays may leave the record (CHECK): a delay outside [lo, hi]
@@ -367,18 +418,43 @@ __device__ __forceinline__ void load_group(ConstEntry E, hodmas_chan_entry (&e)[
 // this group's waits also wait for them), then roots, powers and the sums.
 // With M == 2 each delay also serves the lane's mirror pixel, whose samples
 // sit `moff` bytes further on in the LDS (the mirrored rows).  `zero`: the
-// LDS byte address of the zero pair (CHECK).
-template <int K, bool CF, bool COMP, bool CHECK, bool HALF, int M, int NS = n_sums<K, CF>()>
+// LDS byte address of the zero pair (CHECK).  SH > 0: delays shared along
+// translated pixels (see Shared): `sh` holds the group's first element's delay
+// on entry and the next group's on return; (u2f, qf) are the lane's pixel
+// moved 16 - 3*SH columns to the left; ro / ron: the LDS row offsets of this
+// group's slots and, loaded with the next group's constants, of the next.
+template <int K, bool CF, bool COMP, bool CHECK, bool HALF, int M, int SH, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], float u2, float q,
                                               const float* __restrict__ lds, int moff, int zero, float (&s)[M][NS],
                                               float (&P)[M][NS], bool more, ConstEntry En,
-                                              hodmas_chan_entry (&en)[4])
+                                              hodmas_chan_entry (&en)[4], Shared& sh, float u2f, float qf,
+                                              const int (&ro)[4], ConstStage Sn, int slot_n, int stride,
+                                              int (&ron)[4])
 {
     Tap tp[4];
     float s0[M][4], s1[M][4], v[M][4];
+    if constexpr (SH > 0) {
+        static_assert(!CHECK && M == 1, "shared delays: untested tiles, one pixel per lane");
+        static_assert(4 * SH == 16, "a group of four elements spans one row of 16 lanes");
+        // e[3] at the moved pixel: off - ro = 4 floor(anchor delay), so addr is 4 floor(delay)
+        const Tap tf = locate_at(e[3], u2f, qf, e[3].off - ro[3]);
+        XF* b = sh.buf;
+        wave_lds_order();                 // the previous group's reads of the buffer come first
+        b[0] = XF{tf.addr, tf.f};
+        b[16] = XF{sh.x, sh.f};
+        wave_lds_order();
+        const XF d1 = b[16 - SH], d2 = b[16 - 2 * SH], d3 = b[16 - 3 * SH];
+        tp[0] = Tap{0.f, sh.f, sh.x + ro[0]};
+        tp[1] = Tap{0.f, d1.f, d1.x + ro[1]};
+        tp[2] = Tap{0.f, d2.f, d2.x + ro[2]};
+        tp[3] = Tap{0.f, d3.f, d3.x + ro[3]};
+        sh.x = tf.addr;
+        sh.f = tf.f;
+    } else {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        tp[m] = locate(e[m], u2, q);
+        for (int m = 0; m < 4; ++m)
+            tp[m] = locate(e[m], u2, q);
+    }
     if (CHECK) {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -403,8 +479,11 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
 #pragma unroll
     for (int mm = 0; mm < M; ++mm)
         asm volatile("" ::"v"(v[mm][0]), "v"(v[mm][1]), "v"(v[mm][2]), "v"(v[mm][3]) : "memory");
-    if (more)
+    if (more) {
         load_group(En, en);
+        if constexpr (SH > 0)
+            load_rowoff(Sn, slot_n, stride, ron);
+    }
 #pragma unroll
     for (int mm = 0; mm < M; ++mm) {
         float T[4][NS];
@@ -439,10 +518,11 @@ __device__ __forceinline__ void after_group(int& groups, float (&s)[M][NS], floa
 // The n elements of this wave's split group in one staged chunk (their
 // constants stored contiguously), four at a time; two constant sets alternate
 // so nothing is copied between them.
-template <int K, bool CF, bool COMP, bool CHECK, bool HALF, int M, int NS = n_sums<K, CF>()>
+template <int K, bool CF, bool COMP, bool CHECK, bool HALF, int M, int SH, int NS = n_sums<K, CF>()>
 __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, float q,
                                                  const float* __restrict__ lds, int moff, int zero, float (&s)[M][NS],
-                                                 float (&c)[M][NS])
+                                                 float (&c)[M][NS], ConstStage St, int stride, float u2f, float qf,
+                                                 XF* shbuf)
 {
     float P[M][NS];
 #pragma unroll
@@ -454,17 +534,28 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
     int sl = 0;
     if (n >= 4) {
         hodmas_chan_entry ea[4], eb[4];
+        int ra[4] = {0, 0, 0, 0}, rb[4] = {0, 0, 0, 0};
+        Shared sh{0, 0.f, shbuf};
         load_group(E, ea);
+        if constexpr (SH > 0) {
+            // slots 0..3 of the chunk; the first element's delay computed in full
+            load_rowoff(St, 0, stride, ra);
+            const Tap t0 = locate_at(ea[0], u2, q, ea[0].off - ra[0]);
+            sh.x = t0.addr;
+            sh.f = t0.f;
+        }
         int groups = 0;
         while (true) {
             const bool more_a = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK, HALF, M>(ea, u2, q, lds, moff, zero, s, P, more_a, E + sl + 4, eb);
+            process_group<K, CF, COMP, CHECK, HALF, M, SH>(ea, u2, q, lds, moff, zero, s, P, more_a, E + sl + 4, eb,
+                                                           sh, u2f, qf, ra, St, sl + 4, stride, rb);
             after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_a)
                 break;
             const bool more_b = sl + 8 <= n;
-            process_group<K, CF, COMP, CHECK, HALF, M>(eb, u2, q, lds, moff, zero, s, P, more_b, E + sl + 4, ea);
+            process_group<K, CF, COMP, CHECK, HALF, M, SH>(eb, u2, q, lds, moff, zero, s, P, more_b, E + sl + 4, ea,
+                                                           sh, u2f, qf, rb, St, sl + 4, stride, ra);
             after_group<NS, COMP, M>(groups, s, c, P);
             sl += 4;
             if (!more_b)
@@ -524,7 +615,7 @@ __device__ __forceinline__ R newton(const R (&p)[K])
 // symmetric about x = 0 (checked on the host), that pixel's delay to element
 // n-1-i equals this pixel's delay to element i, so one delay serves both and
 // the mirror pixel gathers from the mirrored rows the staging fills.
-template <int K, int DT, bool COMP, bool CF, int M, bool CHECK>
+template <int K, int DT, bool COMP, bool CF, int M, bool CHECK, int SH = 0>
 __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_tile_desc& td,
                                              float* __restrict__ lds)
 {
@@ -564,6 +655,18 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
     const double w = A.z0s + iz * A.dzs - td.za;
     const float u2 = (float)(2.0 * u);
     const float q = (float)(u * u + w * (w + 2.0 * td.za));
+    // SH > 0: the same pixel moved 16 - 3*SH columns to the left (the plan
+    // keeps every tile 16 columns wide, so no lane's column was clamped)
+    float u2f = 0.f, qf = 0.f;
+    XF* shbuf = nullptr;
+    if constexpr (SH > 0) {
+        const double uf = u + (3 * SH - 16) * A.dxs;
+        u2f = (float)(2.0 * uf);
+        qf = (float)(uf * uf + w * (w + 2.0 * td.za));
+        // the row's 32-entry buffer after the staged rows (pixel row pl / 16 of
+        // the workgroup; no lane's column was clamped, see above)
+        shbuf = reinterpret_cast<XF*>(reinterpret_cast<char*>(lds) + A.shift_off) + (pl >> 4) * 32 + lx;
+    }
 
     float s[M][NS], c[M][NS];
 #pragma unroll
@@ -591,7 +694,8 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
         for (int h = 0; h < g; ++h)
             goff += (nch - h + A.split - 1) / A.split;
         const int ng = nch > g ? (nch - g + A.split - 1) / A.split : 0;
-        accumulate_chunk<K, CF, COMP, CHECK, kHalf, M>(E + c0 + goff, ng, u2, q, lds, moff, zero, s, c);
+        accumulate_chunk<K, CF, COMP, CHECK, kHalf, M, SH>(E + c0 + goff, ng, u2, q, lds, moff, zero, s, c, St + c0,
+                                                            row_stride(td.window), u2f, qf, shbuf);
     }
 
     if (A.split > 1) {
@@ -662,10 +766,17 @@ template <int K, int DT, bool COMP, bool CF = false, int M = 1>
 __device__ __forceinline__ void form_tile(const FrameArgs& A, int tile, float* __restrict__ lds)
 {
     const hodmas_tile_desc td = load_const(A.tiles, tile);
-    if (td.check)
+    if (td.check) {
         process_tile<K, DT, COMP, CF, M, true>(A, td, lds);
-    else
+    } else {
+        if constexpr (M == 1 && !CF && K >= 2) {
+            if (A.shift == 4 && td.iz0 >= A.shift_iz0) {
+                process_tile<K, DT, COMP, CF, M, false, 4>(A, td, lds);
+                return;
+            }
+        }
         process_tile<K, DT, COMP, CF, M, false>(A, td, lds);
+    }
 }
 
 // M == 1: workgroup b forms tile xcd_tile(b).  M == 2: workgroup b forms pair

@@ -23,6 +23,8 @@ FLAG_FORCE_CHECK = 0x4
 FLAG_TUNE_BATCH = 0x8
 FLAG_CF = 0x10
 FLAG_MIRROR = 0x20
+FLAG_NO_SHARE = 0x40
+INFO_SHARED_DELAYS = 0x10000
 
 _DTYPE_NAMES = {"f32": F32, "f16": F16, "i16": I16, "float32": F32, "float16": F16, "int16": I16}
 

@@ -14,7 +14,10 @@ two float32 values is exact); the hardware square root and reciprocal are
 within one ulp of the rounded values, which `bound` adds as |num r| 2^-22 (the
 reciprocal's ulp and the square root's, carried into r, together).
 A mirror-paired plan's right half takes each left pixel's delay to element i
-as its mirror pixel's delay to element n-1-i."""
+as its mirror pixel's delay to element n-1-i.  A plan that shares delays along
+translated pixels (element pitch = four pixel columns) also forms every
+element's delay at the pixel four columns to the left, which serves the next
+element at the lane's own pixel."""
 import numpy as np
 
 from oracle import oracle as O
@@ -37,6 +40,9 @@ def delay_errors(plan, geometry, grid, mirror=False):
     tx = info.tiling.tile_x
     paired = mirror and (info.flags & hodmas.FLAG_MIRROR)
     worst = worst_b = 0.0
+    shared = bool(info.flags & hodmas.INFO_SHARED_DELAYS)
+    # samples of delay by which element i + 1 four columns on may differ from element i
+    pitch_dev = float(np.abs(np.diff(ex) - 4.0 * grid.dx_m).max()) / lam if shared else 0.0
     for td in tiles:
         if paired and td.ix0 // tx >= (grid.nx // tx) // 2:
             continue                      # right half: formed from the left tiles' delays
@@ -70,6 +76,26 @@ def delay_errors(plan, geometry, grid, mirror=False):
             dx = xp[None, :] - ex[el][:, None]
             exact = geometry.fs_hz * (np.sqrt(dx * dx + zp[None, :] ** 2) / geometry.sound_speed_m_s) - t0s
             err = np.abs(T0 + t - exact)
+            worst = max(worst, float(err.max()))
+            worst_b = max(worst_b, float((err + np.abs(num * r) * 2.0 ** -22).max()))
+        # (tiles whose first row lies shallower than 16 pixel columns compute every delay)
+        if shared and not td.check and grid.z0_m + td.iz0 * grid.dz_m >= 16.0 * grid.dx_m:
+            # delays shared along translated pixels: every element's delay is
+            # also formed at the pixel four columns to the left and handed to
+            # the pixel / element pair it equals exactly (one element on, four
+            # columns on), up to the array's deviation from a 4-column pitch
+            uf = u - 4.0 * dxs
+            u2f = _r32(2.0 * uf)
+            qf = _r32(uf * uf + w * (w + 2.0 * td.za))
+            num = _r32(u2f[None, :] * a + qf[None, :])
+            d = _r32(np.sqrt(np.abs(_r32(d0sq + num))))
+            r = _r32(1.0 / _r32(d + d0))
+            t = _r32(num * r + frac0)
+            xp = grid.x0_m + (ixs - 4) * grid.dx_m
+            zp = grid.z0_m + izs * grid.dz_m
+            dx = xp[None, :] - ex[ch][:, None]
+            exact = geometry.fs_hz * (np.sqrt(dx * dx + zp[None, :] ** 2) / geometry.sound_speed_m_s) - t0s
+            err = np.abs(T0 + t - exact) + pitch_dev
             worst = max(worst, float(err.max()))
             worst_b = max(worst_b, float((err + np.abs(num * r) * 2.0 ** -22).max()))
     return worst, worst_b

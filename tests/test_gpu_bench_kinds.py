@@ -277,13 +277,15 @@ def test_direct_rows_equal_register_staging(hd):
     plans copies its FP32 rows straight into LDS; FLAG_FORCE_CHECK sends every
     tile through the register staging and the per-delay range test instead.
     Both stage the same stored values and test nothing that can fail here, so
-    the images must agree bit for bit, per frame and as batch kinds."""
+    the images must agree bit for bit, per frame and as batch kinds.  (Both
+    compute every delay in full: FLAG_NO_SHARE.)"""
     f = ph.config_frame(2)
     arr = ph.to_fp32(f.rf)
     dev = torch.from_numpy(arr).cuda()
     for mirror in (0, hd.FLAG_MIRROR):
-        fast = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, flags=mirror)
-        tested = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, flags=mirror | hd.FLAG_FORCE_CHECK)
+        full = mirror | hd.FLAG_NO_SHARE
+        fast = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, flags=full)
+        tested = hd.Plan(f.geometry, f.grid, arr.shape[1], "f32", max_order=6, flags=full | hd.FLAG_FORCE_CHECK)
         assert fast.info().lds_bytes == tested.info().lds_bytes
         info = fast.info()
         for k in (1, 3, 6):
@@ -305,13 +307,15 @@ def test_direct_rows_equal_register_staging(hd):
 def test_direct_fp16_rows_against_register_staging(hd):
     """FP16 rows copied straight into LDS (low halves of LDS words, widened by
     the interpolation) against FLAG_FORCE_CHECK plans (rows widened through
-    registers, every delay tested), config-2 geometry with FP16 storage."""
+    registers, every delay tested), config-2 geometry with FP16 storage; every
+    delay computed in full on both sides (FLAG_NO_SHARE)."""
     f = ph.config_frame(2)
     half = ph.to_fp16(f.rf)
     dev = torch.from_numpy(half).cuda()
     for mirror in (0, hd.FLAG_MIRROR):
-        fast = hd.Plan(f.geometry, f.grid, half.shape[1], "f16", max_order=6, flags=mirror)
-        tested = hd.Plan(f.geometry, f.grid, half.shape[1], "f16", max_order=6, flags=mirror | hd.FLAG_FORCE_CHECK)
+        full = mirror | hd.FLAG_NO_SHARE
+        fast = hd.Plan(f.geometry, f.grid, half.shape[1], "f16", max_order=6, flags=full)
+        tested = hd.Plan(f.geometry, f.grid, half.shape[1], "f16", max_order=6, flags=full | hd.FLAG_FORCE_CHECK)
         for k in (1, 3, 6):
             a = fast.beamform(dev, k).cpu().numpy().astype(np.float64)
             b = tested.beamform(dev, k).cpu().numpy().astype(np.float64)
@@ -327,3 +331,51 @@ def test_direct_fp16_rows_against_register_staging(hd):
             assert err <= 1e-6
         fast.close()
         tested.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_shared_delays_against_full_delays(hd, config2, config2_bounds, dtype):
+    """Delays shared along translated pixels (config 2: element pitch = four
+    pixel columns) against the same plan computing every delay: per frame and
+    batched, every order, both within the kernel bar of the oracle (sign-change
+    pixels from the band of the shared plan's own delay bound), the FP32 images
+    of the first frames also pixel by pixel within the error bound, and the two
+    forms within the kernel bar of each other away from sign changes (they
+    round each delay differently)."""
+    frames, oracle_image, band = config2
+    geom, grid = frames[0].geometry, frames[0].grid
+    S = frames[0].rf.shape[1]
+    shared = hd.Plan(geom, grid, S, dtype, max_order=6)
+    full = hd.Plan(geom, grid, S, dtype, max_order=6, flags=hd.FLAG_NO_SHARE)
+    assert shared.info().flags & hd.INFO_SHARED_DELAYS
+    assert not full.info().flags & hd.INFO_SHARED_DELAYS
+    eps = plan_eps(shared, geom, grid)
+    n = 2
+    data = [stored(frames[b].rf, dtype, seed=2000 + b)[0] for b in range(n)]
+    devs = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in data]
+    info = shared.info()
+    bt = hd.Batch(max_frames=n, max_units=info.n_tiles * n, max_lds_bytes=info.lds_bytes)
+    outs = [torch.empty((grid.nz, grid.nx), dtype=torch.float32, device="cuda") for _ in range(n)]
+    for k in ORDERS:
+        bt.set([shared] * n, devs, [k] * n, outs)
+        bt.launch()
+        torch.cuda.synchronize()
+        for b in range(n):
+            a = shared.beamform(devs[b], k).cpu().numpy()
+            assert np.array_equal(outs[b].cpu().numpy(), a), "k=%d frame %d: batch differs" % (k, b)
+            c = full.beamform(devs[b], k).cpu().numpy().astype(np.float64)
+            o = oracle_image((dtype, b), data[b], k)
+            err, _ = band_error(band((dtype, b), data[b], eps), a, k, o, "%s frame %d" % (dtype, b))
+            assert err <= KERNEL_BAR[dtype], "k=%d frame %d rel L2 %.3e" % (k, b, err)
+            off = np.abs(a - c) > 1e-5 * np.abs(c).max()
+            apart = rel_l2(a.astype(np.float64)[~off], c[~off])
+            q = EB.worst_ratio(a, o, config2_bounds[(b, k)]) if dtype == "f32" else float("nan")
+            say("  shared vs full delays %s k=%d frame %d: rel L2 %.2e from the oracle (band), %.2e apart "
+                "(%d pixels on sign changes), %.3f of the pixel bound" % (dtype, k, b, err, apart, int(off.sum()), q))
+            assert off.mean() <= 1e-3
+            assert apart <= KERNEL_BAR[dtype]
+            if dtype == "f32":
+                assert q <= 1.0
+    bt.close()
+    shared.close()
+    full.close()

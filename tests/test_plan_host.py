@@ -175,7 +175,14 @@ def test_default_tiling_and_info():
     assert inf.active_pairs == 32 * 32 * 128           # no element is out of the record here
     # rows of the window and two floats more (the first row's hold the zeros
     # that delays outside the record read)
-    assert inf.lds_bytes == inf.tiling.chunk * (inf.max_window + 2) * 4
+    # (plus, as the plan shares delays along translated pixels, 32 eight-byte
+    # entries per row of 16 lanes)
+    staged = inf.tiling.chunk * (inf.max_window + 2) * 4
+    assert inf.flags & hodmas.INFO_SHARED_DELAYS
+    assert inf.lds_bytes == (staged + 7) // 8 * 8 + 16 * 32 * 8
+    full = _plan(f.geometry, f.grid, 2048, flags=hodmas.FLAG_NO_SHARE)
+    assert full.info().lds_bytes == staged
+    full.close()
     small = _plan(ph.config_frame(1).geometry, ph.config_frame(1).grid, 1024)
     assert small.info().tiling.split in (2, 4)
     p.close()
@@ -374,3 +381,41 @@ def test_batch_set_rejects_host_images_before_any_launch():
     with pytest.raises(ValueError, match="GPU tensor"):
         bt.set([plan], [rf], [1], [wrong])
     plan.close()
+
+
+def test_shared_delays_only_where_the_translation_holds():
+    """Delays are shared along translated pixels only when consecutive
+    elements are exactly four pixel columns apart, tiles are 16 columns wide
+    with one element group, nx is a multiple of 16 and the plan forms pixels
+    one per lane without weighting."""
+    f = ph.config_frame(2)                  # pitch 0.3 mm = 4 x 0.075 mm columns
+    g, gr = f.geometry, f.grid
+
+    def shared(geom=g, grid=gr, **kw):
+        p = _plan(geom, grid, 2048, **kw)
+        on = bool(p.info().flags & hodmas.INFO_SHARED_DELAYS)
+        p.close()
+        return on
+
+    assert shared()
+    assert shared(dtype="f16")
+    assert not shared(flags=hodmas.FLAG_NO_SHARE)
+    assert not shared(flags=hodmas.FLAG_MIRROR)          # pairs take another path
+    assert not shared(flags=hodmas.FLAG_CF)
+    assert not shared(tiling=(32, 8, 1, 0))
+    assert not shared(tiling=(16, 8, 2, 0))
+    # pitch of two columns (config 1), and a grid 8 columns narrower
+    assert not shared(ph.config_frame(1).geometry, ph.config_frame(1).grid)
+    narrow = ph.Grid(nx=gr.nx - 8, nz=gr.nz, x0_m=gr.x0_m + 4 * gr.dx_m, dx_m=gr.dx_m, z0_m=gr.z0_m, dz_m=gr.dz_m)
+    assert not shared(grid=narrow)
+    # element positions given explicitly: shared while uniform at four columns, not once one moves
+    x = (np.arange(g.n_elements) - (g.n_elements - 1) / 2.0) * g.pitch_m
+    assert shared(ph.Geometry(g.n_elements, element_x_m=x))
+    x[40] += 1e-9
+    assert not shared(ph.Geometry(g.n_elements, element_x_m=x))
+    # 1024^2 (config 3): 4096 tiles, 3 rounds over 256 CUs at six workgroups
+    # per CU; the buffers' LDS would leave five, and four rounds
+    f3 = ph.config_frame(3)
+    p3 = _plan(f3.geometry, f3.grid, 2048, "f16")
+    assert not p3.info().flags & hodmas.INFO_SHARED_DELAYS
+    p3.close()
