@@ -149,7 +149,7 @@ typedef struct hodmas_plan_s* hodmas_plan_t;
  * element group, nx is a multiple of 16 and each tile's contributing elements
  * are consecutive, an unpaired, unweighted plan's kernels compute, from
  * order 2 on, one delay per lane for every four elements and take the other
- * three from neighbouring lanes through 32 eight-byte LDS entries per row of
+ * three from neighbouring lanes through 48 eight-byte LDS entries per row of
  * 16 lanes (included in hodmas_plan_info.lds_bytes), unless that LDS would
  * leave a one-frame launch needing more rounds of workgroups over the
  * device's 256 CUs (HODMAS_INFO_SHARED_DELAYS in hodmas_plan_info.flags says

@@ -430,9 +430,10 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
     p->shift_iz0 = shared_first_row(p);
     p->lds_unshared = p->lds_bytes;
     if (p->shift) {
-        // each row of 16 lanes passes delays through 32 (4 floor(delay), fraction) entries
+        // each row of 16 lanes passes delays through 32 (4 floor(delay), fraction)
+        // entries, the rows 48 entries apart (no LDS bank shared by two rows)
         const int32_t off = (int32_t)((staged_bytes(p->tiling.chunk, p->max_window, rows) + 7) / 8 * 8);
-        const int64_t with = std::max<int64_t>(p->lds_bytes, off + block / 16 * 32 * 8);
+        const int64_t with = std::max<int64_t>(p->lds_bytes, off + block / 16 * 48 * 8);
         // The buffers take LDS; where that leaves fewer workgroups per CU and a
         // one-frame launch then needs more rounds of workgroups over the CUs
         // (a 1024^2 grid: 16 tiles per CU, 3 rounds at 6 per CU, 4 at 5), the

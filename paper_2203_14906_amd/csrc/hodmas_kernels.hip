@@ -128,11 +128,16 @@ __device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, floa
 // 16 - 3*SH columns to the left, which is also element i + 4's at the lane's
 // own pixel (the next group's first element).  A group of four elements then
 // computes one delay per lane instead of four, and passes the others between
-// the lanes of a row through a 32-entry LDS buffer: F in entries [0, 16),
+// the lanes of a row through 32 entries of an LDS buffer: F in entries [0, 16),
 // element i's own delays in [16, 32), so element i + s of lane j is entry
 // 16 + j - s*SH.  The shared quantities are 4 floor(delay) as an absolute
 // sample index and the fraction; each element adds the byte offset that its
 // LDS row gives sample 0.
+// Rows' buffers are 48 entries apart: a 64-bit LDS access serves 32 lanes --
+// two rows -- at once, and 16 entries of one row fill half the banks, so the
+// neighbouring row's entries start half the banks (128 bytes) further on.
+constexpr int kRowEntries = 48;
+
 struct XF {
     int x;      // 4 floor(delay), absolute sample index
     float f;    // fraction of the delay
@@ -663,9 +668,9 @@ __device__ __forceinline__ void process_tile(const FrameArgs& A, const hodmas_ti
         const double uf = u + (3 * SH - 16) * A.dxs;
         u2f = (float)(2.0 * uf);
         qf = (float)(uf * uf + w * (w + 2.0 * td.za));
-        // the row's 32-entry buffer after the staged rows (pixel row pl / 16 of
+        // the row's buffer after the staged rows (pixel row pl / 16 of
         // the workgroup; no lane's column was clamped, see above)
-        shbuf = reinterpret_cast<XF*>(reinterpret_cast<char*>(lds) + A.shift_off) + (pl >> 4) * 32 + lx;
+        shbuf = reinterpret_cast<XF*>(reinterpret_cast<char*>(lds) + A.shift_off) + (pl >> 4) * kRowEntries + lx;
     }
 
     float s[M][NS], c[M][NS];

@@ -175,11 +175,11 @@ def test_default_tiling_and_info():
     assert inf.active_pairs == 32 * 32 * 128           # no element is out of the record here
     # rows of the window and two floats more (the first row's hold the zeros
     # that delays outside the record read)
-    # (plus, as the plan shares delays along translated pixels, 32 eight-byte
+    # (plus, as the plan shares delays along translated pixels, 48 eight-byte
     # entries per row of 16 lanes)
     staged = inf.tiling.chunk * (inf.max_window + 2) * 4
     assert inf.flags & hodmas.INFO_SHARED_DELAYS
-    assert inf.lds_bytes == (staged + 7) // 8 * 8 + 16 * 32 * 8
+    assert inf.lds_bytes == (staged + 7) // 8 * 8 + 16 * 48 * 8
     full = _plan(f.geometry, f.grid, 2048, flags=hodmas.FLAG_NO_SHARE)
     assert full.info().lds_bytes == staged
     full.close()
