@@ -138,7 +138,7 @@ __device__ __forceinline__ Tap locate(const hodmas_chan_entry& e, float u2, floa
 // neighbouring row's entries start half the banks (128 bytes) further on.
 constexpr int kRowEntries = 48;
 
-struct XF {
+struct alignas(8) XF {     // one 64-bit LDS access per entry
     int x;      // 4 floor(delay), absolute sample index
     float f;    // fraction of the delay
 };
