@@ -379,3 +379,35 @@ def test_shared_delays_against_full_delays(hd, config2, config2_bounds, dtype):
     bt.close()
     shared.close()
     full.close()
+
+
+def test_shared_and_full_plans_in_one_batch(hd, config2):
+    """One batch holding a plan that shares delays along translated pixels,
+    the same plan computing every delay (the same kind, so both run at the
+    kind's larger LDS) and a mirror-paired plan: every image equals its own
+    per-frame launch bit for bit, at order 1 (where nothing is shared) and at
+    orders 4 and 6."""
+    frames, _, _ = config2
+    geom, grid = frames[0].geometry, frames[0].grid
+    S = frames[0].rf.shape[1]
+    plans = [hd.Plan(geom, grid, S, "f32", max_order=6),
+             hd.Plan(geom, grid, S, "f32", max_order=6, flags=hd.FLAG_NO_SHARE),
+             hd.Plan(geom, grid, S, "f32", max_order=6, flags=hd.FLAG_MIRROR)]
+    assert plans[0].info().flags & hd.INFO_SHARED_DELAYS
+    assert not plans[1].info().flags & hd.INFO_SHARED_DELAYS
+    devs = [torch.from_numpy(ph.to_fp32(frames[b].rf)).cuda() for b in range(3)]
+    bt = hd.Batch(max_frames=3, max_units=sum(p.info().n_tiles for p in plans),
+                  max_lds_bytes=max(p.info().lds_bytes for p in plans))
+    outs = [torch.empty((grid.nz, grid.nx), dtype=torch.float32, device="cuda") for _ in plans]
+    for k in (1, 4, 6):
+        for o in outs:
+            o.fill_(float("nan"))
+        bt.set(plans, devs, [k] * 3, outs)
+        bt.launch()
+        torch.cuda.synchronize()
+        for i, (p, d, o) in enumerate(zip(plans, devs, outs)):
+            assert torch.equal(o, p.beamform(d, k)), "k=%d plan %d" % (k, i)
+        say("shared, full and paired plans in one batch k=%d: each equals its own launch" % k)
+    bt.close()
+    for p in plans:
+        p.close()
