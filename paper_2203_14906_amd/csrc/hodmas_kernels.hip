@@ -146,6 +146,8 @@ struct alignas(8) XF {     // one 64-bit LDS access per entry
 struct Shared {
     int x;      // the group's first element at the lane's pixel
     float f;
+    int fx;     // F: the next group's first element at the lane's pixel
+    float ff;
     XF* buf;    // the lane's entry j of its row's buffer
 };
 
@@ -441,20 +443,15 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
     if constexpr (SH > 0) {
         static_assert(!CHECK && M == 1, "shared delays: untested tiles, one pixel per lane");
         static_assert(4 * SH == 16, "a group of four elements spans one row of 16 lanes");
-        // e[3] at the moved pixel: off - ro = 4 floor(anchor delay), so addr is 4 floor(delay)
-        const Tap tf = locate_at(e[3], u2f, qf, e[3].off - ro[3]);
-        XF* b = sh.buf;
-        wave_lds_order();                 // the previous group's reads of the buffer come first
-        b[0] = XF{tf.addr, tf.f};
-        b[16] = XF{sh.x, sh.f};
+        // the buffer holds this group's F and first element (written at the
+        // end of the previous group, or before the first)
+        const XF* b = sh.buf;
         wave_lds_order();
         const XF d1 = b[16 - SH], d2 = b[16 - 2 * SH], d3 = b[16 - 3 * SH];
         tp[0] = Tap{0.f, sh.f, sh.x + ro[0]};
         tp[1] = Tap{0.f, d1.f, d1.x + ro[1]};
         tp[2] = Tap{0.f, d2.f, d2.x + ro[2]};
         tp[3] = Tap{0.f, d3.f, d3.x + ro[3]};
-        sh.x = tf.addr;
-        sh.f = tf.f;
     } else {
 #pragma unroll
         for (int m = 0; m < 4; ++m)
@@ -507,6 +504,23 @@ __device__ __forceinline__ void process_group(const hodmas_chan_entry (&e)[4], f
             }
         }
     }
+    if constexpr (SH > 0) {
+        if (more) {
+            // the next group's F -- its last element at the moved pixel --
+            // formed here, after this group's arithmetic has been issued, so
+            // its latency and that of the next group's constants overlap it;
+            // written over this group's entries, whose reads came first
+            const Tap tf = locate_at(en[3], u2f, qf, en[3].off - ron[3]);
+            XF* b = sh.buf;
+            wave_lds_order();
+            b[0] = XF{tf.addr, tf.f};
+            b[16] = XF{sh.fx, sh.ff};
+            sh.x = sh.fx;
+            sh.f = sh.ff;
+            sh.fx = tf.addr;
+            sh.ff = tf.f;
+        }
+    }
 }
 
 template <int NS, bool COMP, int M>
@@ -540,14 +554,21 @@ __device__ __forceinline__ void accumulate_chunk(ConstEntry E, int n, float u2, 
     if (n >= 4) {
         hodmas_chan_entry ea[4], eb[4];
         int ra[4] = {0, 0, 0, 0}, rb[4] = {0, 0, 0, 0};
-        Shared sh{0, 0.f, shbuf};
+        Shared sh{0, 0.f, 0, 0.f, shbuf};
         load_group(E, ea);
         if constexpr (SH > 0) {
-            // slots 0..3 of the chunk; the first element's delay computed in full
+            // slots 0..3 of the chunk: the first element's delay computed in
+            // full, and the first group's F
             load_rowoff(St, 0, stride, ra);
             const Tap t0 = locate_at(ea[0], u2, q, ea[0].off - ra[0]);
+            const Tap tf = locate_at(ea[3], u2f, qf, ea[3].off - ra[3]);
             sh.x = t0.addr;
             sh.f = t0.f;
+            sh.fx = tf.addr;
+            sh.ff = tf.f;
+            wave_lds_order();
+            sh.buf[0] = XF{tf.addr, tf.f};
+            sh.buf[16] = XF{t0.addr, t0.f};
         }
         int groups = 0;
         while (true) {
