@@ -126,10 +126,10 @@ typedef struct {
     int32_t tile_z;              /* pixels per tile along z */
     int32_t split;               /* wave groups sharing one pixel's elements: 1, 2 or 4 */
     int32_t chunk;               /* elements staged in LDS at a time; 0: as many as
-                                    fit 40 KB, so four workgroups share a CU, or, in
-                                    an unpaired plan whose one-frame launch then
-                                    needs fewer rounds of workgroups over the CUs,
-                                    20 KB (eight per CU); equal chunks either way */
+                                    fit 40 KB, so four workgroups share a CU, or,
+                                    where a one-frame launch then needs fewer rounds
+                                    of workgroups over the CUs, 20 KB (eight per
+                                    CU); equal chunks either way */
 } hodmas_tiling;
 
 typedef struct hodmas_plan_s* hodmas_plan_t;

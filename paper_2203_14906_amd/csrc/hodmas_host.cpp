@@ -416,12 +416,13 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         delete p;
         return HODMAS_EUNSUPPORTED;
     }
-    // An unpaired grid with more tiles than one round of workgroups over the
-    // CUs at that size (1024^2: 4096 tiles) takes chunks of at most 20 KB
+    // A grid with more workgroups than one round over the CUs at that size
+    // (1024^2: 4096 tiles, or 2048 mirror pairs) takes chunks of at most 20 KB
     // instead when that needs fewer rounds: eight workgroups per CU, the most
     // a CU holds, outweigh the extra staging rounds (measured 2-16 % faster
     // per frame at 1024^2).
-    if (auto_chunk && !mirror) {
+    if (auto_chunk) {
+        const int64_t units = int64_t(p->tiles.size()) / rows;   // a mirror pair is one workgroup
         const int64_t row_bytes = int64_t(row_stride(p->max_window)) * 4;
         auto lds_at = [&](int64_t c) {
             const int64_t cc = ceil_div(p->tiling.chunk, ceil_div(p->tiling.chunk, c));   // equal chunks
@@ -429,7 +430,7 @@ hodmas_status hodmas_plan(const hodmas_geometry* geometry, const hodmas_grid* gr
         };
         const int64_t at40 = lds_at(std::max<int64_t>(1, cap / row_bytes));
         const int64_t at20 = lds_at(std::max<int64_t>(1, 20 * 1024 / row_bytes));
-        if (launch_rounds(int64_t(p->tiles.size()), at20, block) < launch_rounds(int64_t(p->tiles.size()), at40, block))
+        if (launch_rounds(units, at20, block) < launch_rounds(units, at40, block))
             cap = 20 * 1024;
     }
     if (staged_bytes(p->tiling.chunk, p->max_window, rows) > cap) {
