@@ -419,3 +419,28 @@ def test_shared_delays_only_where_the_translation_holds():
     p3 = _plan(f3.geometry, f3.grid, 2048, "f16")
     assert not p3.info().flags & hodmas.INFO_SHARED_DELAYS
     p3.close()
+
+
+def test_automatic_chunk_takes_fewer_rounds_at_1024():
+    """A 1024^2 grid has 4096 tiles (2048 mirror pairs): at the 40 KB chunk a
+    one-frame launch would need several rounds of workgroups over 256 CUs, so
+    the plan takes equal chunks within 20 KB instead (eight workgroups per
+    CU); config 2's 1024 tiles fit one round either way and keep the 40 KB
+    chunk."""
+    f3 = ph.config_frame(3)
+    for flags in (0, hodmas.FLAG_MIRROR):
+        p = _plan(f3.geometry, f3.grid, 2048, "f16", flags=flags)
+        inf = p.info()
+        rows = 2 if flags else 1
+        staged = inf.tiling.chunk * (inf.max_window + 2) * 4 * rows
+        assert staged <= 20 * 1024 and inf.lds_bytes == staged
+        n_chunks = -(-256 // inf.tiling.chunk)
+        assert n_chunks >= 2 and inf.tiling.chunk == -(-256 // n_chunks)      # equal chunks
+        # the 40 KB cap alone would have taken bigger chunks
+        assert (40 * 1024) // ((inf.max_window + 2) * 4 * rows) > inf.tiling.chunk
+        p.close()
+    f2 = ph.config_frame(2)
+    p = _plan(f2.geometry, f2.grid, 2048, flags=hodmas.FLAG_NO_SHARE)
+    inf = p.info()
+    assert inf.tiling.chunk == 128 and inf.lds_bytes > 20 * 1024
+    p.close()
