@@ -18,6 +18,10 @@ sum over element subsets of signed k-th roots of the delayed samples).
   the bar -- elsewhere the kernel adds no more than its own 2e-5 to it).
 - The reduced-precision workload (256 elements, 1024x1024, int16 and FP16)
   on full images at every order, unpaired and paired, against both oracles.
+- Delays shared along translated pixels (the unpaired plans of this
+  geometry, whose pitch is four pixel columns) against the same plans
+  computing every delay, FP32, FP16 and int16, per frame and batched, and
+  mixed with full-delay and paired plans in one batch.
 - Pixel by pixel, beside the relative L2 bars: the step's first two frames
   (every pixel) and the reduced-precision workload (every 16th row) stay
   within a per-pixel bound from a running error analysis of the kernel's
@@ -411,3 +415,38 @@ def test_shared_and_full_plans_in_one_batch(hd, config2):
     bt.close()
     for p in plans:
         p.close()
+
+
+def test_shared_delays_int16(hd, config2):
+    """int16 codes (rows rescaled through registers) with delays shared along
+    translated pixels, per frame and batched: within the kernel bar of the
+    oracle fed the same codes, at every order, and within that bar of the
+    plan computing every delay."""
+    frames, oracle_image, band = config2
+    geom, grid = frames[0].geometry, frames[0].grid
+    S = frames[0].rf.shape[1]
+    codes, scale = stored(frames[0].rf, "i16", seed=2000)
+    dev = torch.from_numpy(np.ascontiguousarray(codes)).cuda()
+    shared = hd.Plan(geom, grid, S, "i16", max_order=6, dequant_scale=scale)
+    full = hd.Plan(geom, grid, S, "i16", max_order=6, dequant_scale=scale, flags=hd.FLAG_NO_SHARE)
+    assert shared.info().flags & hd.INFO_SHARED_DELAYS
+    eps = plan_eps(shared, geom, grid)
+    info = shared.info()
+    bt = hd.Batch(max_frames=1, max_units=info.n_tiles, max_lds_bytes=info.lds_bytes)
+    out = torch.empty((grid.nz, grid.nx), dtype=torch.float32, device="cuda")
+    for k in ORDERS:
+        a = shared.beamform(dev, k).cpu().numpy()
+        bt.set([shared], [dev], [k], [out])
+        bt.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), a), "k=%d: batch differs" % k
+        o = O.beamform(codes, geom, grid, k, dequant_scale=scale)
+        err, _ = band_error(band(("i16", 0), codes, eps, scale), a, k, o, "i16 shared")
+        c = full.beamform(dev, k).cpu().numpy().astype(np.float64)
+        off = np.abs(a - c) > 1e-5 * np.abs(c).max()
+        apart = rel_l2(a.astype(np.float64)[~off], c[~off])
+        say("  shared delays i16 k=%d: rel L2 %.2e from the oracle (band), %.2e from full delays" % (k, err, apart))
+        assert err <= KERNEL_BAR["i16"] and apart <= KERNEL_BAR["i16"] and off.mean() <= 1e-3
+    bt.close()
+    shared.close()
+    full.close()
